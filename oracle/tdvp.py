@@ -1,0 +1,465 @@
+"""Purified-MPS finite-temperature TD-DMRG, float64 / complex128 reference.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+What is computed (purification / thermal-field-dynamics section, Eqs. for
+rho_beta, |Psi_beta> and C(t)):
+  |I>       = sum_i |i>_P |i>_Q over the one-carrier space (P = physical,
+              Q = auxiliary copy)
+  |Psi_b>   = exp(-beta H / 2) |I>,  Z = <Psi_b|Psi_b>
+  C(t)      = <Psi_b| exp(iHt) j exp(-iHt) j |Psi_b> / Z
+with H acting on P only and inner products over P and Q.  Time evolution is
+the time-dependent variational principle with projector splitting (the
+integrator the paper cites), one-site variant, second-order symmetric sweep.
+
+Site tensors are A[a, p, q, b] (left bond, P leg, Q leg, right bond).
+
+Readings where the paper is silent (they bind the HIP path too):
+  * bond growth: the first n_grow imaginary steps are taken by
+    propagation-and-compression with a fourth-order Taylor polynomial of
+    exp(-dtau H) in Horner form, each stage an exact MPO x MPS product plus a
+    sum, compressed by a left QR sweep and a right-to-left SVD sweep keeping
+    at most D singular values with s/s_max > cutoff and never splitting a
+    multiplet whose relative gap is below 1e-8;
+  * the remaining imaginary steps and all real-time steps are one-site TDVP
+    sweeps: left-to-right with half step, then right-to-left with half step,
+    the last site evolved twice, the bond matrix evolved backwards;
+  * QR gauge with a real non-negative diagonal of R;
+  * Krylov exponential: Lanczos with full (twice-applied classical
+    Gram-Schmidt) reorthogonalisation; stop when beta_k |e_k^T exp(zT_k) e_1|
+    <= tol |exp(zT_k) e_1|, or when the Krylov space is exhausted;
+  * j|Psi_b> is compressed to the same D with the same rule and keeps the norm
+    the truncation leaves.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.linalg import eigh_tridiagonal
+
+from . import model as Mdl
+
+# --------------------------------------------------------------------------
+# MPS containers
+# --------------------------------------------------------------------------
+
+
+class MPS:
+    """List of site tensors A[a, p, q, b]; `log_norm` carries a scalar
+    normalisation factor exp(log_norm) kept outside the tensors."""
+
+    def __init__(self, tensors, log_norm=0.0):
+        self.A = [np.asarray(t, dtype=complex) for t in tensors]
+        self.log_norm = log_norm
+
+    def copy(self):
+        return MPS([a.copy() for a in self.A], self.log_norm)
+
+    def __len__(self):
+        return len(self.A)
+
+    def bond_dims(self):
+        return [a.shape[3] for a in self.A[:-1]]
+
+
+def identity_mps(model):
+    """The purified identity |I> of the one-carrier space (normalised) and
+    0.5 ln <I|I>.  Bond states: 0 = carrier not yet placed, 1 = placed; after
+    the last electronic site only 'placed' survives."""
+    sl = Mdl.site_list(model)
+    dims = Mdl.site_dims(model)
+    e_sites = [i for i, s in enumerate(sl) if s[0] == "e"]
+    first_e, last_e = e_sites[0], e_sites[-1]
+    tensors = []
+    # bond-state labels on the left of each site
+    for i, (kind, n, m) in enumerate(sl):
+        d = dims[i]
+        left = ["none"] if i <= first_e else (["placed"] if i > last_e else ["none", "placed"])
+        right = ["none"] if i < first_e else (["placed"] if i >= last_e else ["none", "placed"])
+        A = np.zeros((len(left), d, d, len(right)), dtype=complex)
+        for ia, a in enumerate(left):
+            for ib, b in enumerate(right):
+                if kind == "e":
+                    if a == "none" and b == "none":
+                        A[ia, 0, 0, ib] = 1.0
+                    elif a == "none" and b == "placed":
+                        A[ia, 1, 1, ib] = 1.0
+                    elif a == "placed" and b == "placed":
+                        A[ia, 0, 0, ib] = 1.0
+                else:
+                    if a == b:
+                        for v in range(d):
+                            A[ia, v, v, ib] = 1.0
+        tensors.append(A)
+    ph = [dims[i] for i, s in enumerate(sl) if s[0] != "e"]
+    dim = model.n_mol * int(np.prod(ph)) if ph else model.n_mol
+    psi = MPS(tensors)
+    # normalise: every component of |I> is 1, so <I|I> = dim
+    psi.A[0] = psi.A[0] / math.sqrt(dim)
+    psi.log_norm = 0.5 * math.log(dim)
+    return psi
+
+
+def full_rank_mps(vec, dims):
+    """Exact MPS of a dense purified vector (site order, P then Q leg per
+    site) with every bond at its largest possible dimension, built by reduced
+    QR sweeps without truncation; the last tensor carries the norm.  At these
+    bond dimensions every tangent-space projector is the identity, so the
+    projector-splitting integrator is exact (tests only)."""
+    L = len(dims)
+    rest = np.asarray(vec, dtype=complex).reshape(1, -1)
+    A = []
+    Dl = 1
+    for i in range(L - 1):
+        d = dims[i]
+        M = rest.reshape(Dl * d * d, -1)
+        Q, R = qr_pos(M)
+        A.append(Q.reshape(Dl, d, d, Q.shape[1]))
+        Dl = Q.shape[1]
+        rest = R
+    d = dims[-1]
+    A.append(rest.reshape(Dl, d, d, 1))
+    return MPS(A)
+
+
+def to_dense(psi):
+    """Dense coefficient array over (p_1 q_1 ... p_L q_L), tiny chains only."""
+    T = psi.A[0]
+    for A in psi.A[1:]:
+        T = np.tensordot(T, A, axes=([T.ndim - 1], [0]))
+    return T.reshape(-1) * math.exp(psi.log_norm)
+
+
+# --------------------------------------------------------------------------
+# Dense linear algebra conventions
+# --------------------------------------------------------------------------
+
+
+def qr_pos(M):
+    """Reduced QR with a real non-negative diagonal of R."""
+    Q, R = np.linalg.qr(M, mode="reduced")
+    d = np.diag(R)
+    ph = np.ones_like(d)
+    nz = np.abs(d) > 0
+    ph[nz] = d[nz] / np.abs(d[nz])
+    Q = Q * ph[None, :]
+    R = np.conj(ph)[:, None] * R
+    return Q, R
+
+
+def lq_pos(M):
+    """M = L Q with Q having orthonormal rows and L's diagonal real >= 0."""
+    Q, R = qr_pos(M.conj().T)
+    return R.conj().T, Q.conj().T
+
+
+def truncation_rank(s, D, cutoff):
+    """How many singular values (sorted descending) to keep."""
+    if s.size == 0 or s[0] == 0.0:
+        return 1
+    k = int(np.sum(s > cutoff * s[0]))
+    k = max(1, min(k, D))
+    # never cut inside a (near-)degenerate multiplet
+    while 1 < k < s.size and (s[k - 1] - s[k]) <= 1e-8 * s[k - 1]:
+        k -= 1
+    return k
+
+
+# --------------------------------------------------------------------------
+# MPO x MPS, sums and compression
+# --------------------------------------------------------------------------
+
+
+def apply_mpo(Ws, psi):
+    """Exact product: bond dimension multiplies by the MPO bond dimension."""
+    out = []
+    for W, A in zip(Ws, psi.A):
+        a, d, _, b = A.shape
+        wl, wr = W.shape[0], W.shape[1]
+        B = np.tensordot(W, A, axes=([3], [1])).transpose(3, 0, 2, 4, 5, 1)
+        out.append(B.reshape(a * wl, d, d, b * wr))
+    return MPS(out, psi.log_norm)
+
+
+def add(psi, phi, c):
+    """psi + c * phi as an exact MPS (block-diagonal bonds).  Both must carry
+    the same log_norm."""
+    assert abs(psi.log_norm - phi.log_norm) < 1e-300 + 1e-15 * max(1, abs(psi.log_norm))
+    L = len(psi)
+    out = []
+    for i, (A, B) in enumerate(zip(psi.A, phi.A)):
+        if i == 0:
+            B = c * B
+        a1, d, _, b1 = A.shape
+        a2, _, _, b2 = B.shape
+        if L == 1:
+            out.append(A + B)
+            continue
+        if i == 0:
+            C = np.zeros((1, d, d, b1 + b2), dtype=complex)
+            C[:, :, :, :b1] = A
+            C[:, :, :, b1:] = B
+        elif i == L - 1:
+            C = np.zeros((a1 + a2, d, d, 1), dtype=complex)
+            C[:a1] = A
+            C[a1:] = B
+        else:
+            C = np.zeros((a1 + a2, d, d, b1 + b2), dtype=complex)
+            C[:a1, :, :, :b1] = A
+            C[a1:, :, :, b1:] = B
+        out.append(C)
+    return MPS(out, psi.log_norm)
+
+
+def compress(psi, D, cutoff):
+    """Left QR sweep, then right-to-left SVD truncation.  Returns a
+    right-canonical MPS whose first tensor carries the norm."""
+    A = [a.copy() for a in psi.A]
+    L = len(A)
+    for i in range(L - 1):
+        a, d, _, b = A[i].shape
+        Q, R = qr_pos(A[i].reshape(a * d * d, b))
+        A[i] = Q.reshape(a, d, d, Q.shape[1])
+        A[i + 1] = np.tensordot(R, A[i + 1], axes=([1], [0]))
+    for i in range(L - 1, 0, -1):
+        a, d, _, b = A[i].shape
+        U, s, Vh = np.linalg.svd(A[i].reshape(a, d * d * b), full_matrices=False)
+        k = truncation_rank(s, D, cutoff)
+        A[i] = Vh[:k].reshape(k, d, d, b)
+        A[i - 1] = np.tensordot(A[i - 1], U[:, :k] * s[None, :k], axes=([3], [0]))
+    return MPS(A, psi.log_norm)
+
+
+def normalize(psi):
+    """For a right-canonical MPS: move the norm of the first tensor into
+    log_norm.  Returns the norm that was removed."""
+    n = np.linalg.norm(psi.A[0])
+    psi.A[0] = psi.A[0] / n
+    psi.log_norm += math.log(n)
+    return n
+
+
+def taylor_growth_step(psi, Hw, dtau, D, cutoff, order=4):
+    """exp(-dtau H) psi by propagation and compression, Taylor order 4 in
+    Horner form: phi <- psi + (-dtau/k) H phi, k = order..1."""
+    phi = psi
+    for k in range(order, 0, -1):
+        Hphi = apply_mpo(Hw, phi)
+        phi = compress(add(psi, Hphi, -dtau / k), D, cutoff)
+    return phi
+
+
+# --------------------------------------------------------------------------
+# Environments and effective Hamiltonians
+# --------------------------------------------------------------------------
+
+
+def left_env(Lenv, bra, W, ket):
+    """L'[c', b', b] = sum conj(bra[a',p',q,b']) L[c,a',a] W[c,c',p',p] ket[a,p,q,b]."""
+    T = np.tensordot(Lenv, ket, axes=([2], [0]))            # [c, a', p, q, b]
+    U = np.tensordot(W, T, axes=([0, 3], [0, 2]))           # [c', p', a', q, b]
+    out = np.tensordot(U, bra.conj(), axes=([2, 1, 3], [0, 1, 2]))  # [c', b, b']
+    return out.transpose(0, 2, 1)
+
+
+def right_env(Renv, bra, W, ket):
+    """R'[c, a', a] = sum ket[a,p,q,b] R[c',b',b] W[c,c',p',p] conj(bra[a',p',q,b'])."""
+    T = np.tensordot(ket, Renv, axes=([3], [2]))            # [a, p, q, c', b']
+    U = np.tensordot(W, T, axes=([1, 3], [3, 1]))           # [c, p', a, q, b']
+    out = np.tensordot(U, bra.conj(), axes=([1, 3, 4], [1, 2, 3]))  # [c, a, a']
+    return out.transpose(0, 2, 1)
+
+
+def heff_apply(Lenv, W, Renv, A):
+    """y[a',p',q,b'] = sum L[c,a',a] W[c,c',p',p] A[a,p,q,b] R[c',b',b]."""
+    T = np.tensordot(Lenv, A, axes=([2], [0]))              # [c, a', p, q, b]
+    U = np.tensordot(W, T, axes=([0, 3], [0, 2]))           # [c', p', a', q, b]
+    y = np.tensordot(U, Renv, axes=([0, 4], [0, 2]))        # [p', a', q, b']
+    return y.transpose(1, 0, 2, 3)
+
+
+def keff_apply(Lenv, Renv, C):
+    """y[a',b'] = sum_c L[c,a',a] C[a,b] R[c,b',b]."""
+    T = np.tensordot(Lenv, C, axes=([2], [0]))              # [c, a', b]
+    return np.tensordot(T, Renv, axes=([0, 2], [0, 2]))
+
+
+# --------------------------------------------------------------------------
+# Krylov exponential
+# --------------------------------------------------------------------------
+
+
+class KrylovNotConverged(RuntimeError):
+    pass
+
+
+def expm_krylov(apply, v, z, tol=1e-14, mmax=40):
+    """exp(z H) v for Hermitian H given as `apply`, by Lanczos with full
+    reorthogonalisation.  Returns (result, number of Krylov vectors)."""
+    shape = v.shape
+    v = v.reshape(-1)
+    n = v.size
+    beta0 = np.linalg.norm(v)
+    if beta0 == 0.0:
+        return v.reshape(shape).copy(), 0
+    Q = np.zeros((min(mmax, n) + 1, n), dtype=complex)
+    Q[0] = v / beta0
+    alpha, beta = [], []
+    for k in range(min(mmax, n)):
+        w = apply(Q[k].reshape(shape)).reshape(-1)
+        alpha.append(np.vdot(Q[k], w).real)
+        Qk = Q[:k + 1]
+        for _ in range(2):
+            w = w - Qk.T @ (Qk.conj() @ w)
+        bk = np.linalg.norm(w)
+        a = np.array(alpha)
+        if k == 0:
+            lam, S = a.copy(), np.ones((1, 1))
+        else:
+            lam, S = eigh_tridiagonal(a, np.array(beta))
+        u = S @ (np.exp(z * lam) * S[0, :])
+        exhausted = (k + 1 == n)
+        if exhausted or bk * abs(u[-1]) <= tol * np.linalg.norm(u) or bk == 0.0:
+            return (beta0 * (Q[:k + 1].T @ u)).reshape(shape), k + 1
+        beta.append(bk)
+        Q[k + 1] = w / bk
+    raise KrylovNotConverged(f"Lanczos did not converge in {mmax} steps")
+
+
+# --------------------------------------------------------------------------
+# One-site TDVP, projector splitting, second order
+# --------------------------------------------------------------------------
+
+
+def _boundary(shape_w):
+    e = np.zeros((shape_w, 1, 1), dtype=complex)
+    e[0, 0, 0] = 1.0
+    return e
+
+
+def right_envs(psi, Ws):
+    """R[i] = contraction of sites i..L-1 (R[L] is the boundary)."""
+    L = len(psi)
+    R = [None] * (L + 1)
+    R[L] = _boundary(1)
+    for i in range(L - 1, 0, -1):
+        R[i] = right_env(R[i + 1], psi.A[i], Ws[i], psi.A[i])
+    return R
+
+
+class Stats:
+    def __init__(self):
+        self.krylov = []
+
+
+def tdvp_step(psi, Ws, z, tol=1e-14, mmax=40, stats=None):
+    """One symmetric sweep pair evolving psi by exp(z H): z = -i dt for real
+    time, z = -dtau for imaginary time.  psi must be right-canonical with the
+    centre on site 0; it is returned in the same form."""
+    L = len(psi)
+    A = psi.A
+    R = right_envs(psi, Ws)
+    Lenv = [None] * (L + 1)
+    Lenv[0] = _boundary(1)
+    h = 0.5 * z
+
+    def site_evolve(i):
+        f = lambda x: heff_apply(Lenv[i], Ws[i], R[i + 1], x)
+        A[i], m = expm_krylov(f, A[i], h, tol, mmax)
+        if stats is not None:
+            stats.krylov.append(m)
+
+    # left to right
+    for i in range(L - 1):
+        site_evolve(i)
+        a, d, _, b = A[i].shape
+        Q, C = qr_pos(A[i].reshape(a * d * d, b))
+        A[i] = Q.reshape(a, d, d, Q.shape[1])
+        Lenv[i + 1] = left_env(Lenv[i], A[i], Ws[i], A[i])
+        f = lambda x: keff_apply(Lenv[i + 1], R[i + 1], x)
+        C, m = expm_krylov(f, C, -h, tol, mmax)
+        if stats is not None:
+            stats.krylov.append(m)
+        A[i + 1] = np.tensordot(C, A[i + 1], axes=([1], [0]))
+    site_evolve(L - 1)
+    # right to left
+    site_evolve(L - 1)
+    for i in range(L - 1, 0, -1):
+        a, d, _, b = A[i].shape
+        C, Q = lq_pos(A[i].reshape(a, d * d * b))
+        A[i] = Q.reshape(Q.shape[0], d, d, b)
+        R[i] = right_env(R[i + 1], A[i], Ws[i], A[i])
+        f = lambda x: keff_apply(Lenv[i], R[i], x)
+        C, m = expm_krylov(f, C, -h, tol, mmax)
+        if stats is not None:
+            stats.krylov.append(m)
+        A[i - 1] = np.tensordot(A[i - 1], C, axes=([3], [0]))
+        site_evolve(i - 1)
+    return psi
+
+
+# --------------------------------------------------------------------------
+# Observables
+# --------------------------------------------------------------------------
+
+
+def overlap(bra, Ws, ket):
+    """<bra| O |ket> for an MPO O (ignores log_norm factors)."""
+    E = _boundary(1)
+    for A, W, B in zip(bra.A, Ws, ket.A):
+        E = left_env(E, A, W, B)
+    return E[0, 0, 0]
+
+
+def norm(psi):
+    E = np.ones((1, 1), dtype=complex)
+    for A in psi.A:
+        E = np.einsum("xy,xpqa,ypqb->ab", E, A.conj(), A)
+    return math.sqrt(E[0, 0].real)
+
+
+# --------------------------------------------------------------------------
+# The pipeline
+# --------------------------------------------------------------------------
+
+
+def thermal_prep(model, Hw, beta, n_imag, n_grow, D, cutoff=1e-10, tol=1e-14,
+                 mmax=40, stats=None):
+    """|Psi_beta> = exp(-beta H/2)|I> in n_imag steps of beta/(2 n_imag).
+    Returns the normalised right-canonical state and ln Z."""
+    dtau = beta / (2.0 * n_imag)
+    psi = identity_mps(model)
+    psi = compress(psi, D, cutoff)
+    normalize(psi)
+    for _ in range(n_grow):
+        psi = taylor_growth_step(psi, Hw, dtau, D, cutoff)
+        normalize(psi)
+    for _ in range(n_imag - n_grow):
+        tdvp_step(psi, Hw, -dtau, tol, mmax, stats)
+        normalize(psi)
+    return psi, 2.0 * psi.log_norm
+
+
+def apply_current(Jw, psi, D, cutoff=1e-10):
+    """j|psi> compressed to bond dimension D (norm kept, log_norm reset)."""
+    phi = compress(apply_mpo(Jw, psi), D, cutoff)
+    phi.log_norm = 0.0
+    return phi
+
+
+def corr_current(Hw, Jw, psi_beta, D, dt, n_steps, cutoff=1e-10, tol=1e-14,
+                 mmax=40, stats=None, callback=None):
+    """C(t_k), k = 0..n_steps, t_k = k dt, for a normalised psi_beta."""
+    psi = psi_beta.copy()
+    psi.log_norm = 0.0
+    phi = apply_current(Jw, psi, D, cutoff)
+    C = np.zeros(n_steps + 1, dtype=complex)
+    C[0] = overlap(psi, Jw, phi)
+    for k in range(1, n_steps + 1):
+        tdvp_step(psi, Hw, -1j * dt, tol, mmax, stats)
+        tdvp_step(phi, Hw, -1j * dt, tol, mmax, stats)
+        C[k] = overlap(psi, Jw, phi)
+        if callback is not None:
+            callback(k, psi, phi)
+    return C

@@ -1,0 +1,56 @@
+"""Shared test helpers: seeded models and canonical random MPS built with the
+oracle's conventions (tests only)."""
+import numpy as np
+
+from paper_2003_13245_amd import workloads as W
+
+
+def small_model(n_mol=3, n_loc=1, n_nl=0, levels=3, V=0.7, seed=5, periodic=1):
+    rng = np.random.default_rng(seed)
+    om = list(np.sort(rng.uniform(0.4, 1.5, n_loc)))
+    g = list(rng.uniform(0.3, 1.0, n_loc))
+    on = list(rng.uniform(0.2, 0.9, n_nl))
+    gn = list(rng.uniform(0.1, 0.4, n_nl))
+    return W.Model(n_mol=n_mol, periodic=periodic, omega_loc=om, g_loc=g, omega_nl=on,
+                   g_nl=gn, levels_loc=levels, levels_nl=levels, V=V, R=1.3, e0=1.0)
+
+
+def random_mps(dims, D, rng, center):
+    """Random MPS with bond dims min(D, max rank), left-orthonormal left of
+    `center`, right-orthonormal right of it."""
+    from oracle import tdvp as T
+    L = len(dims)
+    lp, rp = [1.0] * L, [1.0] * L
+    acc = 1.0
+    for i in range(L):
+        acc = min(acc * dims[i] ** 2, 1e18)
+        lp[i] = acc
+    acc = 1.0
+    for i in range(L - 1, -1, -1):
+        acc = min(acc * dims[i] ** 2, 1e18)
+        rp[i] = acc
+    bonds = [int(min(D, lp[i], rp[i + 1])) for i in range(L - 1)]
+    A = []
+    for i in range(L):
+        a = 1 if i == 0 else bonds[i - 1]
+        b = 1 if i == L - 1 else bonds[i]
+        d = dims[i]
+        A.append(rng.standard_normal((a, d, d, b)) + 1j * rng.standard_normal((a, d, d, b)))
+    for i in range(center):
+        a, d, _, b = A[i].shape
+        Q, R = T.qr_pos(A[i].reshape(a * d * d, b))
+        A[i] = Q.reshape(a, d, d, b)
+        A[i + 1] = np.tensordot(R, A[i + 1], axes=([1], [0]))
+    for i in range(L - 1, center, -1):
+        a, d, _, b = A[i].shape
+        Lm, Q = T.lq_pos(A[i].reshape(a, d * d * b))
+        A[i] = Q.reshape(a, d, d, b)
+        A[i - 1] = np.tensordot(A[i - 1], Lm, axes=([3], [0]))
+    A[center] /= np.linalg.norm(A[center])
+    return T.MPS(A)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))

@@ -1,0 +1,367 @@
+"""Pins of the CPU oracle against things other than itself: closed forms,
+exact diagonalisation, exactness properties of the integrator, conservation
+laws and library routines.  CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from helpers import small_model
+from oracle import analysis as An
+from oracle import ed as ED
+from oracle import model as Mdl
+from oracle import mpo as OM
+from oracle import tdvp as T
+from paper_2003_13245_amd import workloads as W
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+
+
+# ---------------------------------------------------------------- operators
+@pytest.mark.parametrize("n_mol,n_loc,n_nl,periodic", [(3, 1, 0, 1), (4, 1, 0, 1), (3, 1, 1, 1),
+                                                       (3, 0, 2, 1), (3, 1, 1, 0), (4, 0, 1, 0)])
+def test_mpo_densifies_to_ed_matrices(n_mol, n_loc, n_nl, periodic):
+    """The MPOs of H and j, densified and restricted to the one-carrier space,
+    equal the matrices written directly from Eq. (1), the Peierls term and the
+    current operator."""
+    m = small_model(n_mol=n_mol, n_loc=n_loc, n_nl=n_nl, levels=2, periodic=periodic)
+    idx = Mdl.one_carrier_basis(m)
+    H, K, _ = ED.build(m)
+    Hd = OM.densify(OM.hamiltonian_mpo(m))
+    Jd = OM.densify(OM.current_mpo(m))
+    assert np.abs(Hd[np.ix_(idx, idx)] - H).max() < 1e-14
+    assert np.abs(Jd[np.ix_(idx, idx)] - (m.e0 * m.R / 1j) * K).max() < 1e-14
+    # H conserves the carrier number: no matrix elements leave the sector
+    mask = np.ones(Hd.shape[0], bool)
+    mask[idx] = False
+    assert np.abs(Hd[np.ix_(mask, idx)]).max() < 1e-14
+
+
+def test_current_is_commutator_with_position_open_chain():
+    """For the open chain j = i [H, e0 R sum_n n c+_n c_n] (the Peierls factor
+    included), which fixes the sign and the factor of the current."""
+    m = small_model(n_mol=4, n_loc=1, n_nl=1, levels=2, periodic=0)
+    H, K, dim = ED.build(m)
+    nph = dim // m.n_mol
+    X = np.kron(np.diag(np.arange(m.n_mol, dtype=float)), np.eye(nph)) * m.e0 * m.R
+    j = (m.e0 * m.R / 1j) * K
+    assert np.abs(1j * (H @ X - X @ H) - j).max() < 1e-13
+
+
+def test_identity_state_is_purified_identity():
+    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2)
+    psi = T.identity_mps(m)
+    v = T.to_dense(psi)
+    dims = Mdl.site_dims(m)
+    L = len(dims)
+    # interleaved (p1 q1 p2 q2 ...) -> (P, Q) matrix
+    t = v.reshape([d for d in dims for _ in range(2)])
+    t = np.transpose(t, list(range(0, 2 * L, 2)) + list(range(1, 2 * L, 2)))
+    n = int(np.prod(dims))
+    M = t.reshape(n, n)
+    idx = Mdl.one_carrier_basis(m)
+    ref = np.zeros((n, n))
+    ref[idx, idx] = 1.0
+    assert np.abs(M - ref).max() < 1e-13
+    assert abs(2 * psi.log_norm - math.log(len(idx))) < 1e-13
+
+
+# ---------------------------------------------------------------- ED pins
+def test_tight_binding_closed_form():
+    """g = 0: j commutes with H, C(t) = <j^2> = 4/(1 + cosh 2) for N = 4,
+    V = beta = 1, at every t, real."""
+    m = W.Model(n_mol=4, periodic=1, omega_loc=[1.0], g_loc=[0.0], omega_nl=[], g_nl=[],
+                levels_loc=3, levels_nl=1, V=1.0)
+    r = ED.EDResult(m, 1.0)
+    C = r.corr(np.linspace(0, 20, 41))
+    ref = GOLD["tight_binding_N4_V1_beta1"]["value"]
+    assert abs(ref - 4 / (1 + math.cosh(2))) < 1e-15
+    assert np.abs(C - ref).max() < 1e-12
+    assert abs(An.tight_binding_corr(4, 1.0, 1.0) - ref) < 1e-14
+    # Z factorises: electrons x truncated oscillators
+    k = 2 * np.pi * np.arange(4) / 4
+    z_e = np.exp(-2 * np.cos(k)).sum()
+    z_ph = sum(math.exp(-v) for v in range(3)) ** 4
+    assert abs(r.logZ - math.log(z_e * z_ph)) < 1e-12
+
+
+def test_ed_c0_and_time_reversal():
+    m = small_model(n_mol=3, n_loc=1, n_nl=1, levels=3)
+    r = ED.EDResult(m, 0.8)
+    t = np.linspace(0, 7, 15)
+    C = r.corr(t)
+    Cm = r.corr(-t)
+    assert np.abs(Cm - C.conj()).max() < 1e-12
+    rho = (r.U * r.w) @ r.U.T
+    assert abs(C[0] - np.trace(rho @ r.j @ r.j)) < 1e-12
+    assert abs(C[0].imag) < 1e-13 and C[0].real > 0
+    # beta = 0: C(0) = 2 (e0 V R)^2 + Peierls fluctuation (Holstein only here)
+    mh = small_model(n_mol=4, n_loc=1, n_nl=0, levels=3)
+    r0 = ED.EDResult(mh, 0.0)
+    assert abs(r0.corr([0.0])[0] - 2 * (mh.e0 * mh.V * mh.R) ** 2) < 1e-12
+
+
+def test_ed_thermal_density_is_uniform():
+    m = small_model(n_mol=4, n_loc=1, n_nl=0, levels=3)
+    r = ED.EDResult(m, 1.3)
+    assert np.abs(r.density_expectation() - 0.25).max() < 1e-12
+
+
+def test_fermi_golden_rule_limit():
+    """V -> 0: C(t)/V^2 approaches the hopping-limit closed form (derived
+    reading of the printed formula, see oracle.analysis.fgr_corr).  The first
+    correction is linear in V; a wrong sign of Im C, a missing factor 2 or a
+    missing g^2 doubling gives an O(1) mismatch."""
+    w, g, beta = 1.0, 0.5, 1.0
+    t = np.linspace(0, 12, 25)
+    errs, conj_errs = [], []
+    for V in (1e-2, 1e-3):
+        m = W.Model(n_mol=3, periodic=1, omega_loc=[w], g_loc=[g], omega_nl=[], g_nl=[],
+                    levels_loc=12, levels_nl=1, V=V)
+        C = ED.EDResult(m, beta).corr(t) / V ** 2
+        F = An.fgr_corr(t, V, [w], [g], beta) / V ** 2
+        errs.append(np.abs(C - F).max() / np.abs(F).max())
+        conj_errs.append(np.abs(C - F.conj()).max() / np.abs(F).max())
+    assert errs[1] < 2e-3
+    assert errs[1] < errs[0] / 5
+    assert min(conj_errs) > 0.3          # the printed (conjugate) time dependence
+
+
+# ------------------------------------------------------------- oracle algebra
+def test_qr_and_lq_conventions():
+    rng = np.random.default_rng(0)
+    M = rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4))
+    Q, R = T.qr_pos(M)
+    assert np.allclose(Q @ R, M, atol=1e-14)
+    assert np.allclose(Q.conj().T @ Q, np.eye(4), atol=1e-14)
+    assert np.all(np.abs(np.diag(R).imag) < 1e-15) and np.all(np.diag(R).real >= 0)
+    assert np.allclose(np.tril(R, -1), 0)
+    L, Qr = T.lq_pos(M.T)
+    assert np.allclose(L @ Qr, M.T, atol=1e-14)
+    assert np.allclose(Qr @ Qr.conj().T, np.eye(4), atol=1e-14)
+    assert np.all(np.diag(L).real >= 0) and np.allclose(np.triu(L, 1), 0)
+
+
+@pytest.mark.parametrize("z", [-0.3j, -0.7, 0.25 + 0.1j])
+def test_krylov_expm_matches_dense_expm(z):
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((60, 60)) + 1j * rng.standard_normal((60, 60))
+    H = (A + A.conj().T) / 4
+    v = rng.standard_normal(60) + 1j * rng.standard_normal(60)
+    y, m = T.expm_krylov(lambda x: H @ x, v, z, tol=1e-14, mmax=60)
+    ref = sla.expm(z * H) @ v
+    assert np.abs(y - ref).max() / np.abs(ref).max() < 1e-12
+    assert m < 60
+
+
+def test_krylov_exhausted_space_is_exact():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((5, 5))
+    H = A + A.T
+    v = rng.standard_normal(5).astype(complex)
+    y, m = T.expm_krylov(lambda x: H @ x, v, -2.0j, tol=1e-30, mmax=40)
+    assert m == 5
+    assert np.abs(y - sla.expm(-2.0j * H) @ v).max() < 1e-12
+
+
+def test_truncation_rule_keeps_multiplets_whole():
+    s = np.array([1.0, 0.5, 0.5 * (1 - 1e-12), 0.2, 1e-12])
+    assert T.truncation_rank(s, 2, 1e-10) == 1
+    assert T.truncation_rank(s, 3, 1e-10) == 3
+    assert T.truncation_rank(s, 10, 1e-10) == 4
+    assert T.truncation_rank(np.array([0.0, 0.0]), 4, 1e-10) == 1
+
+
+def test_compress_without_truncation_is_exact():
+    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2)
+    Jw = OM.current_mpo(m)
+    psi = T.identity_mps(m)
+    X = T.apply_mpo(Jw, psi)
+    Y = T.compress(X, 10 ** 6, 0.0)
+    assert np.abs(T.to_dense(Y) - T.to_dense(X)).max() < 1e-13
+
+
+def test_mps_add_and_taylor_growth_against_dense():
+    """One growth step equals the fourth-order Taylor polynomial of
+    exp(-dtau H) applied to |I> when nothing is truncated."""
+    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2)
+    Hw = OM.hamiltonian_mpo(m)
+    psi = T.compress(T.identity_mps(m), 10 ** 6, 0.0)
+    dtau = 0.07
+    out = T.taylor_growth_step(psi, Hw, dtau, 10 ** 6, 0.0)
+    Hfull = OM.densify(Hw)
+    dims = Mdl.site_dims(m)
+    L = len(dims)
+    n = int(np.prod(dims))
+    # H acts on the P legs of the interleaved dense vector
+    v = T.to_dense(psi).reshape([d for d in dims for _ in range(2)])
+    v = np.transpose(v, list(range(0, 2 * L, 2)) + list(range(1, 2 * L, 2))).reshape(n, n)
+    P = np.eye(n)
+    term = np.eye(n)
+    for k in range(1, 5):
+        term = term @ (-dtau * Hfull) / k
+        P = P + term
+    ref = (P @ v).reshape([d for d in dims] * 2)
+    ref = np.transpose(ref, [x for i in range(L) for x in (i, L + i)]).reshape(-1)
+    assert np.abs(T.to_dense(out) - ref).max() < 1e-13
+
+
+# ---------------------------------------------------------- integrator pins
+def _full_rank_setup():
+    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2, V=0.6)
+    dims = Mdl.site_dims(m)
+    return m, dims, OM.hamiltonian_mpo(m), OM.current_mpo(m)
+
+
+def test_full_rank_tdvp_equals_exact_thermal_prep():
+    """At maximal bond dimension every projector is the identity and the
+    projector-splitting integrator is exact: imaginary-time TDVP from |I>
+    reproduces ln Z of exact diagonalisation."""
+    m, dims, Hw, _ = _full_rank_setup()
+    beta, n = 1.2, 6
+    psi0 = T.identity_mps(m)
+    psi = T.full_rank_mps(T.to_dense(psi0), dims)
+    psi.log_norm = 0.0
+    # full_rank_mps leaves the norm on the last site; sweep it to site 0
+    psi = T.MPS(psi.A)
+    A = psi.A
+    for i in range(len(A) - 1, 0, -1):
+        a, d, _, b = A[i].shape
+        Lm, Q = T.lq_pos(A[i].reshape(a, d * d * b))
+        A[i] = Q.reshape(a, d, d, b)
+        A[i - 1] = np.tensordot(A[i - 1], Lm, axes=([3], [0]))
+    T.normalize(psi)
+    for _ in range(n):
+        T.tdvp_step(psi, Hw, -beta / (2 * n))
+        T.normalize(psi)
+    logz = 2 * psi.log_norm
+    r = ED.EDResult(m, beta)
+    assert abs(logz - r.logZ) < 1e-10
+
+
+def test_full_rank_tdvp_real_time_equals_ed():
+    m, dims, Hw, Jw = _full_rank_setup()
+    beta = 0.9
+    r = ED.EDResult(m, beta)
+    # exact purified thermal state, then j|psi>, both at full rank
+    psi0 = T.identity_mps(m)
+    v0 = T.to_dense(psi0)
+    L = len(dims)
+    n = int(np.prod(dims))
+    Hfull = OM.densify(Hw)
+    Jfull = OM.densify(Jw)
+    Mb = sla.expm(-0.5 * beta * Hfull)
+
+    def act(Op, v):
+        t = v.reshape([d for d in dims for _ in range(2)])
+        t = np.transpose(t, list(range(0, 2 * L, 2)) + list(range(1, 2 * L, 2))).reshape(n, n)
+        t = (Op @ t).reshape(dims + dims)
+        return np.transpose(t, [x for i in range(L) for x in (i, L + i)]).reshape(-1)
+
+    vb = act(Mb, v0)
+    vb = vb / np.linalg.norm(vb)
+    vj = act(Jfull, vb)
+
+    def canon(v):
+        p = T.full_rank_mps(v, dims)
+        A = p.A
+        for i in range(len(A) - 1, 0, -1):
+            a, d, _, b = A[i].shape
+            Lm, Q = T.lq_pos(A[i].reshape(a, d * d * b))
+            A[i] = Q.reshape(a, d, d, b)
+            A[i - 1] = np.tensordot(A[i - 1], Lm, axes=([3], [0]))
+        return p
+
+    psi, phi = canon(vb), canon(vj)
+    dt, ns = 0.2, 10
+    C = [T.overlap(psi, Jw, phi)]
+    for _ in range(ns):
+        T.tdvp_step(psi, Hw, -1j * dt)
+        T.tdvp_step(phi, Hw, -1j * dt)
+        C.append(T.overlap(psi, Jw, phi))
+    ref = r.corr(np.arange(ns + 1) * dt)
+    assert np.abs(np.array(C) - ref).max() < 1e-10
+
+
+def test_norm_and_energy_conserved_in_real_time():
+    m = small_model(n_mol=3, n_loc=1, n_nl=1, levels=2)
+    Hw = OM.hamiltonian_mpo(m)
+    psi, _ = T.thermal_prep(m, Hw, 1.0, 4, 4, 6)
+    e0 = T.overlap(psi, Hw, psi).real
+    n0 = T.norm(psi)
+    for _ in range(10):
+        T.tdvp_step(psi, Hw, -0.15j)
+    assert abs(T.norm(psi) - n0) < 1e-12
+    assert abs(T.overlap(psi, Hw, psi).real - e0) < 1e-10
+
+
+def test_g0_correlation_constant_under_tdvp():
+    """g = 0: j commutes with H, so C(t) = C(0) = 4/(1 + cosh 2) exactly.  The
+    truncated TDVP trajectory drifts only by integrator error, which shrinks
+    as the step is refined."""
+    m = W.Model(n_mol=4, periodic=1, omega_loc=[1.0], g_loc=[0.0], omega_nl=[], g_nl=[],
+                levels_loc=2, levels_nl=1, V=1.0)
+    Hw, Jw = OM.hamiltonian_mpo(m), OM.current_mpo(m)
+    psi, logz = T.thermal_prep(m, Hw, 1.0, 10, 10, 12)
+    ref = GOLD["tight_binding_N4_V1_beta1"]["value"]
+    drift = []
+    for dt, n in ((0.2, 8), (0.05, 32)):
+        C = T.corr_current(Hw, Jw, psi, 12, dt, n)
+        assert abs(C[0] - ref) < 1e-5
+        drift.append(np.abs(C - C[0]).max())
+    assert drift[1] < drift[0] / 3
+    assert drift[1] < 2e-6
+
+
+def test_thermal_prep_converges_to_ed_with_bond_dimension():
+    wl = W.tiny_fp64()
+    m = wl.model
+    Hw = OM.hamiltonian_mpo(m)
+    r = ED.EDResult(m, 1.0)
+    errs = []
+    for D in (2, 4, 8):
+        psi, logz = T.thermal_prep(m, Hw, 1.0, 8, 8, D)
+        errs.append(abs(logz - r.logZ))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 5e-3
+
+
+def test_translation_invariance_of_thermal_density():
+    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2)
+    Hw = OM.hamiltonian_mpo(m)
+    psi, _ = T.thermal_prep(m, Hw, 1.0, 6, 6, 64)      # untruncated (max bond 35)
+    idx = Mdl.index_of(m)
+    for n in range(3):
+        Nw = OM.build_mpo(m, [(1.0, [(idx[("e", n, -1)], "n")])])
+        assert abs(T.overlap(psi, Nw, psi) - 1 / 3) < 1e-12
+
+
+# --------------------------------------------------------------- mobility
+def test_mobility_quadrature_and_units():
+    tau, dt, n, beta = 3.0, 0.01, 3001, 2.0
+    t = np.arange(n) * dt
+    C = np.exp(-t / tau) * (1 + 0.3j)
+    mu, mu_cm = An.mobility(C, dt, beta)
+    exact = beta * tau * (1 - math.exp(-t[-1] / tau))
+    assert abs(mu - exact) / exact < 1e-5
+    assert abs(An.MOBILITY_AU_CM2VS - GOLD["mobility_au_in_cm2_per_Vs"]["value"]) < 1e-11
+    assert abs(mu_cm / mu - An.MOBILITY_AU_CM2VS) < 1e-15
+    lmfp, v, tau_e = An.mean_free_path(C, dt)
+    assert abs(v - 1.0) < 1e-15 and abs(tau_e - exact / beta) / tau < 1e-5
+
+
+# --------------------------------------------------------------- workloads
+def test_workloads_are_seeded_and_in_range():
+    a, b = W.headline(), W.headline()
+    assert a.model.to_json() == b.model.to_json()
+    lam = sum(g * g * w for g, w in zip(a.model.g_loc, a.model.omega_loc))
+    assert abs(lam - W.mev(150.0)) < 1e-15
+    for w in a.model.omega_loc + a.model.omega_nl:
+        assert W.cm1(50.0) <= w <= W.cm1(1600.0)
+    assert abs(a.run.beta - 1052.58) < 0.01
+    assert abs(W.fs(0.5) - 20.67) < 0.01
+    c2 = W.fp64_chain()
+    assert all(0.2 <= g * g <= 1.0 for g in c2.model.g_loc)
