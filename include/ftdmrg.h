@@ -1,0 +1,237 @@
+/*
+ * ftdmrg — finite-temperature TD-DMRG for carrier mobility on AMD MI355X (gfx950).
+ *
+ * C ABI of the hot path of the method of "Finite Temperature TD-DMRG for the
+ * Carrier Mobility of Organic Semiconductors" (J. Phys. Chem. Lett. 2020):
+ * a purified thermal state |Psi_beta> = exp(-beta H / 2)|I> is prepared by
+ * imaginary-time evolution, |Psi_beta> and j|Psi_beta> are propagated in real
+ * time with the one-site projector-splitting time-dependent variational
+ * principle, and the current-current correlation
+ *     C(t) = <Psi_beta| exp(iHt) j exp(-iHt) j |Psi_beta> / Z
+ * is integrated by the Kubo formula into the mobility mu.
+ *
+ * Conventions (all calls):
+ *   - Atomic units (hbar = e0 = k_B = 1 unless e0 is given).  Conversions from
+ *     cm^-1, meV, K or fs happen in the caller.
+ *   - Every call returns an ftd_status.  Outputs are unspecified when the
+ *     status is not FTD_OK.  ftd_last_error() returns a thread-local message.
+ *   - No exceptions cross the ABI.  Handles are not thread-safe: use one
+ *     context per host thread.
+ *   - Device work is enqueued on the context's HIP stream.  Calls that return
+ *     host values (log Z, C(t), norms, statistics) synchronise that stream.
+ *   - Complex numbers in host buffers are interleaved (re, im) doubles.
+ */
+#ifndef FTDMRG_H
+#define FTDMRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ftd_status;
+#define FTD_OK 0
+#define FTD_EINVAL 1     /* invalid argument (shape, range, non-finite value)  */
+#define FTD_ENOMEM 2     /* device allocation failed                           */
+#define FTD_EDEVICE 3    /* HIP runtime error                                  */
+#define FTD_ENOCONV 4    /* Krylov exponential not converged / non-finite data */
+#define FTD_ESTATE 5     /* handle in the wrong state (e.g. precision mismatch)*/
+
+typedef enum {
+    FTD_C128 = 0,        /* every contraction in complex float64               */
+    FTD_C64 = 1,         /* contractions in complex float32 on MFMA, Krylov,
+                            QR, norms and log Z in float64                     */
+    FTD_BF16X3 = 2       /* contractions as three bf16 split products with
+                            float32 accumulation; float64 elsewhere            */
+} ftd_precision;
+
+typedef struct ftd_ctx ftd_ctx;
+typedef struct ftd_mpo ftd_mpo;
+typedef struct ftd_mps ftd_mps;
+
+/* Optional device allocator (e.g. a framework's caching allocator).
+ * alloc returns NULL on failure. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} ftd_allocator;
+
+/* The (Holstein-)Peierls chain: Eq. (1) of the paper, and the Holstein-Peierls
+ * coupling of its closing section.  N molecules on a ring (periodic = 1) or an
+ * open chain; each molecule carries n_loc local modes (frequency omega_loc[m],
+ * dimensionless Holstein coupling g_loc[m]); each bond (n, n+1) carries n_nl
+ * non-local modes (omega_nl[m], Peierls coupling g_nl[m]).  Each mode keeps
+ * `levels` harmonic-oscillator number states.  One carrier.  V is the transfer
+ * integral, R the inter-molecular distance and e0 the carrier charge, both of
+ * which scale the current operator j = (e0 R / i) sum_n (V + sum_m g_nl[m]
+ * omega_nl[m] x_{n,m}) (c+_{n+1} c_n - c+_n c_{n+1}).
+ * Arrays are borrowed and copied during ftd_mpo_build. */
+typedef struct {
+    int32_t n_mol;
+    int32_t n_loc;
+    int32_t n_nl;
+    int32_t periodic;
+    int32_t levels_loc;
+    int32_t levels_nl;
+    const double* omega_loc;   /* [n_loc] */
+    const double* g_loc;       /* [n_loc] */
+    const double* omega_nl;    /* [n_nl]  */
+    const double* g_nl;        /* [n_nl]  */
+    double V;
+    double R;
+    double e0;
+} ftd_model;
+
+/* Krylov exponential settings: Lanczos with full reorthogonalisation (float64),
+ * stopped when beta_k |e_k^T exp(zT_k) e_1| <= tol |exp(zT_k) e_1| or when
+ * the Krylov space is exhausted; more than mmax vectors -> FTD_ENOCONV. */
+typedef struct {
+    double tol;
+    int32_t mmax;
+} ftd_krylov_opts;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a borrowed
+ * hipStream_t (NULL = the null stream).  `alloc` may be NULL (hipMalloc). */
+ftd_status ftd_ctx_create(int32_t device, void* hip_stream, const ftd_allocator* alloc,
+                          ftd_ctx** out);
+void ftd_ctx_destroy(ftd_ctx* ctx);
+const char* ftd_last_error(void);
+
+/* Kernel timing: when enabled, every launch of the effective-Hamiltonian
+ * contraction kernels is bracketed by HIP events on the context stream.
+ * ftd_ctx_stats synchronises and returns, for the contraction kernels of the
+ * H_eff / K_eff matvecs since the last reset: number of launches, summed
+ * kernel milliseconds and summed algorithmic flops (8 m n k per complex
+ * product); and over the whole context the number of matvecs and Krylov
+ * vectors.  Statistics are reset by ftd_ctx_stats_reset. */
+typedef struct {
+    int64_t heff_launches;
+    double heff_ms;
+    double heff_flops;
+    int64_t dom_launches;      /* the single kernel with the largest share */
+    double dom_ms;
+    double dom_flops;
+    double dom_bytes;          /* algorithmic bytes of that kernel's operands */
+    int64_t matvecs;
+    int64_t krylov_vectors;
+    int64_t expm_calls;
+    int64_t krylov_max;
+} ftd_stats;
+ftd_status ftd_ctx_set_timing(ftd_ctx* ctx, int32_t enable);
+ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out);
+ftd_status ftd_ctx_stats_reset(ftd_ctx* ctx);
+ftd_status ftd_ctx_synchronize(ftd_ctx* ctx);
+
+/* ------------------------------------------------------------------- MPO */
+
+/* Build the MPOs of H (Eq. (1) plus the Peierls term) and of the current j
+ * (the operator written with the Kubo formula, generalised by the Peierls
+ * factor).  Site order: e_0, the local modes of molecule 0, the bond modes of
+ * bond (0,1), e_1, ...; the wrap-bond modes follow molecule N-1.
+ * Errors: FTD_EINVAL for n_mol < 3 on a ring (the two hops of a 2-ring
+ * coincide), n_mol < 2 open, levels < 1 where modes exist, non-finite
+ * parameters.  H and J belong to the caller (ftd_mpo_destroy). */
+ftd_status ftd_mpo_build(ftd_ctx* ctx, const ftd_model* model, ftd_mpo** H, ftd_mpo** J);
+void ftd_mpo_destroy(ftd_mpo* mpo);
+/* Number of sites, and per-site physical dimension d (host array, n_sites). */
+ftd_status ftd_mpo_info(const ftd_mpo* mpo, int32_t* n_sites, int32_t* dims, int32_t* bond_w);
+
+/* ------------------------------------------------------------------- MPS */
+
+/* Purified MPS: site tensors A[a][p][q][b] (left bond, P leg, Q leg, right
+ * bond), float64 complex on the device.  A scalar log-norm factor is kept
+ * outside the tensors. */
+void ftd_mps_destroy(ftd_mps* psi);
+ftd_status ftd_mps_copy(ftd_ctx* ctx, const ftd_mps* src, ftd_mps** out);
+/* bond_dims receives n_sites - 1 values. */
+ftd_status ftd_mps_info(const ftd_mps* psi, int32_t* n_sites, int32_t* bond_dims,
+                        double* log_norm, int32_t* precision);
+/* Host copies of one site tensor, interleaved complex, row-major [a][p][q][b].
+ * `count` is the number of complex elements the host buffer holds. */
+ftd_status ftd_mps_get_site(ftd_ctx* ctx, const ftd_mps* psi, int32_t site, double* host,
+                            int64_t count);
+/* Build an MPS from host tensors: dims[4*i..4*i+3] = (Dl, d, d, Dr) of site i;
+ * tensors concatenated in site order, interleaved complex. */
+ftd_status ftd_mps_from_host(ftd_ctx* ctx, int32_t n_sites, const int32_t* dims,
+                             const double* host, double log_norm, ftd_precision prec,
+                             ftd_mps** out);
+/* <psi|psi> of the tensors (log_norm excluded), float64. */
+ftd_status ftd_mps_norm(ftd_ctx* ctx, const ftd_mps* psi, double* out);
+
+/* ------------------------------------------------------- the hot path calls */
+
+/* Imaginary-time preparation (purification section of the paper):
+ * |Psi_beta> = exp(-beta H / 2)|I> from the purified identity |I> of the
+ * one-carrier space, in n_imag steps of dtau = beta / (2 n_imag).  The first
+ * n_grow steps are propagation-and-compression steps (fourth-order Taylor in
+ * Horner form, each stage an exact MPO x MPS product compressed to at most D
+ * singular values with s/s_max > cutoff); the remaining steps are one-site
+ * TDVP sweeps.  If n_grow < 0 the growth continues until every bond has
+ * reached min(D, its maximal rank) or n_imag steps are used.
+ * Output: the normalised state (right-canonical, centre on site 0; caller
+ * owns it) and ln Z, Z = <Psi_beta|Psi_beta>.  Errors: FTD_EINVAL (beta < 0,
+ * n_imag < 1, D < 1), FTD_ENOCONV, FTD_ENOMEM. */
+ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t n_imag,
+                            int32_t n_grow, int32_t D, double cutoff, ftd_precision prec,
+                            const ftd_krylov_opts* ko, ftd_mps** psi_beta, double* log_Z);
+
+/* One second-order one-site TDVP projector-splitting step, in place:
+ * psi <- exp(z H) psi with z = -i dt_real - dt_imag (real time: dt_imag = 0,
+ * imaginary time: dt_real = 0).  psi must be right-canonical with its centre
+ * on site 0 (as every call here leaves it).  Contractions run in psi's
+ * precision.  Errors: FTD_ENOCONV (Krylov or non-finite), FTD_EINVAL. */
+ftd_status ftd_tdvp_step(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt_real,
+                         double dt_imag, const ftd_krylov_opts* ko);
+
+/* Exact MPO x MPS product followed by compression to D (s/s_max > cutoff):
+ * out = compress(O psi).  Used for j|Psi_beta>.  out belongs to the caller. */
+ftd_status ftd_apply_compress(ftd_ctx* ctx, const ftd_mpo* O, const ftd_mps* psi, int32_t D,
+                              double cutoff, ftd_mps** out);
+
+/* <bra| O |ket> (log_norm factors excluded), complex, host out[2]. */
+ftd_status ftd_overlap(ftd_ctx* ctx, const ftd_mps* bra, const ftd_mpo* O, const ftd_mps* ket,
+                       double* out);
+
+/* C(t_k), k = 0..n_steps, t_k = k dt, for a normalised psi_beta (not
+ * mutated): phi = compress(j psi_beta, D); then per step one TDVP step of psi
+ * and of phi and C_k = <psi|j|phi>.  C_out: host, 2*(n_steps+1) doubles. */
+ftd_status ftd_corr_current(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mpo* J,
+                            const ftd_mps* psi_beta, int32_t D, double cutoff, double dt,
+                            int32_t n_steps, const ftd_krylov_opts* ko, double* C_out);
+
+/* Kubo formula: mu = (1/(2 k_B T e0)) int C(t) dt over the whole real line,
+ * evaluated as (beta/e0) int_0^{t_max} Re C(t) dt with C(-t) = conj(C(t)),
+ * trapezoid rule on the uniform grid of n samples (interleaved complex C).
+ * mu_cm2Vs uses 1 a.u. of mobility = e a0^2 / hbar (CODATA 2018).
+ * Host-only.  Errors: FTD_EINVAL (n < 2, dt <= 0, beta < 0). */
+ftd_status ftd_mobility(const double* C, int32_t n, double dt, double beta, double e0,
+                        double* mu_au, double* mu_cm2Vs);
+
+/* ------------------------------------------------- kernel-level entry points
+ * Apply the one-site effective Hamiltonian of `site` to x, with the left
+ * environment built from sites < site of psi (assumed left-orthonormal there)
+ * and the right environment from sites > site (right-orthonormal), exactly as
+ * inside ftd_tdvp_step.  x, y: host interleaved complex of psi's site shape.
+ * n_repeat > 1 repeats the product (timing).  Used by the parity tests and the
+ * roofline measurement. */
+ftd_status ftd_heff_apply(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, int32_t site,
+                          const double* x, double* y, int32_t n_repeat);
+
+/* Complex GEMM on the device kernels: C = op(A) op(B) with op = identity,
+ * transpose or conjugate transpose per operand (trans = 0, 1, 2), M x N
+ * result, inner dimension K; host buffers interleaved complex, row-major:
+ * A is M x K (trans 0) or K x M (trans 1, 2), B is K x N (0) or N x K (1, 2).
+ * precision FTD_C128 (float64) or FTD_C64 (float32 operands, float64 out).
+ * Used by the kernel parity tests. */
+ftd_status ftd_gemm(ftd_ctx* ctx, int32_t precision, int32_t M, int32_t N, int32_t K,
+                    int32_t transA, int32_t transB, const double* A, const double* B, double* C);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

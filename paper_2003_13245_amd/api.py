@@ -1,0 +1,265 @@
+"""Python face of libftdmrg.so (include/ftdmrg.h): argument marshalling only.
+
+Names follow the C ABI: mpo_build, thermal_prep, tdvp_step, corr_current,
+mobility, plus the kernel-level entry points used by the tests and the
+benchmark.  torch supplies the HIP stream and (optionally) the device
+allocator; all computation happens in the native library, which must be
+built: importing this module raises ImportError otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import FtdError, PRECISION, check, lib
+
+__all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step",
+           "corr_current", "mobility", "apply_compress", "overlap", "heff_apply",
+           "mps_from_host", "gemm", "FtdError"]
+
+
+class Context:
+    """One library context on a HIP device, bound to a HIP stream.
+
+    stream: an integer hipStream_t, or None for torch's current stream on the
+    device (torch required), or 0 for the null stream.
+    use_torch_allocator: route device allocations through torch's caching
+    allocator."""
+
+    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = True):
+        self._alloc = None
+        alloc_p = None
+        if stream is None or use_torch_allocator:
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream(device).cuda_stream
+            if use_torch_allocator:
+                dev = device
+
+                def _a(nbytes, user):
+                    try:
+                        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self._stream)
+                    except Exception:
+                        return None
+
+                def _f(ptr, user):
+                    torch.cuda.caching_allocator_delete(ptr)
+
+                self._afn = _abi.ALLOC_FN(_a)
+                self._ffn = _abi.FREE_FN(_f)
+                self._alloc = _abi.Allocator(self._afn, self._ffn, None)
+                alloc_p = C.byref(self._alloc)
+        self._stream = int(stream)
+        self.device = device
+        h = C.c_void_p()
+        check(lib.ftd_ctx_create(device, C.c_void_p(self._stream), alloc_p, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        """Release the context.  Handles created from it keep a reference to
+        this object, so the native context is destroyed only after the last of
+        them is gone."""
+        self._closed = True
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib.ftd_ctx_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def synchronize(self):
+        check(lib.ftd_ctx_synchronize(self.h))
+
+    def set_timing(self, on: bool):
+        check(lib.ftd_ctx_set_timing(self.h, int(bool(on))))
+
+    def stats_reset(self):
+        check(lib.ftd_ctx_stats_reset(self.h))
+
+    def stats(self) -> dict:
+        s = _abi.Stats()
+        check(lib.ftd_ctx_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in _abi.Stats._fields_}
+
+
+class Mpo:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def info(self):
+        n = C.c_int32()
+        check(lib.ftd_mpo_info(self.h, C.byref(n), None, None))
+        dims = np.zeros(n.value, dtype=np.int32)
+        w = np.zeros(max(1, n.value - 1), dtype=np.int32)
+        check(lib.ftd_mpo_info(self.h, C.byref(n), dims.ctypes.data_as(_abi.I32P),
+                               w.ctypes.data_as(_abi.I32P)))
+        return dims, w[: n.value - 1]
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib.ftd_mpo_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Mps:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def info(self):
+        n = C.c_int32()
+        check(lib.ftd_mps_info(self.h, C.byref(n), None, None, None))
+        bd = np.zeros(max(1, n.value - 1), dtype=np.int32)
+        ln = C.c_double()
+        pr = C.c_int32()
+        check(lib.ftd_mps_info(self.h, C.byref(n), bd.ctypes.data_as(_abi.I32P), C.byref(ln),
+                               C.byref(pr)))
+        return {"n_sites": n.value, "bond_dims": bd[: n.value - 1].tolist(),
+                "log_norm": ln.value, "precision": pr.value}
+
+    def site(self, i: int, shape) -> np.ndarray:
+        n = int(np.prod(shape))
+        buf = np.zeros(2 * n, dtype=np.float64)
+        check(lib.ftd_mps_get_site(self.ctx.h, self.h, int(i), _abi._dptr(buf), n))
+        return (buf[0::2] + 1j * buf[1::2]).reshape(shape)
+
+    def copy(self):
+        h = C.c_void_p()
+        check(lib.ftd_mps_copy(self.ctx.h, self.h, C.byref(h)))
+        return Mps(self.ctx, h)
+
+    def norm2(self) -> float:
+        out = C.c_double()
+        check(lib.ftd_mps_norm(self.ctx.h, self.h, C.byref(out)))
+        return out.value
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib.ftd_mps_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def _model_struct(model):
+    keep = []
+
+    def arr(x):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+        if a.size == 0:
+            a = np.zeros(1)
+        keep.append(a)
+        return a.ctypes.data_as(_abi.DP)
+
+    m = _abi.Model(int(model.n_mol), len(model.omega_loc), len(model.omega_nl),
+                   int(model.periodic), int(model.levels_loc), int(model.levels_nl),
+                   arr(model.omega_loc), arr(model.g_loc), arr(model.omega_nl),
+                   arr(model.g_nl), float(model.V), float(model.R), float(model.e0))
+    return m, keep
+
+
+def mpo_build(ctx: Context, model):
+    """MPOs of H and of the current j for a workloads.Model."""
+    m, keep = _model_struct(model)
+    H, J = C.c_void_p(), C.c_void_p()
+    check(lib.ftd_mpo_build(ctx.h, C.byref(m), C.byref(H), C.byref(J)))
+    return Mpo(ctx, H), Mpo(ctx, J)
+
+
+def thermal_prep(ctx, H, beta, n_imag, n_grow, D, cutoff=1e-10, precision="c128",
+                 tol=1e-14, mmax=40):
+    psi = C.c_void_p()
+    logz = C.c_double()
+    ko = _abi._krylov(tol, mmax)
+    check(lib.ftd_thermal_prep(ctx.h, H.h, float(beta), int(n_imag), int(n_grow), int(D),
+                               float(cutoff), PRECISION[precision], C.byref(ko), C.byref(psi),
+                               C.byref(logz)))
+    return Mps(ctx, psi), logz.value
+
+
+def tdvp_step(ctx, H, psi, dt_real=0.0, dt_imag=0.0, tol=1e-14, mmax=40):
+    ko = _abi._krylov(tol, mmax)
+    check(lib.ftd_tdvp_step(ctx.h, H.h, psi.h, float(dt_real), float(dt_imag), C.byref(ko)))
+
+
+def apply_compress(ctx, O, psi, D, cutoff=1e-10):
+    out = C.c_void_p()
+    check(lib.ftd_apply_compress(ctx.h, O.h, psi.h, int(D), float(cutoff), C.byref(out)))
+    return Mps(ctx, out)
+
+
+def overlap(ctx, bra, O, ket) -> complex:
+    out = np.zeros(2)
+    check(lib.ftd_overlap(ctx.h, bra.h, O.h, ket.h, _abi._dptr(out)))
+    return complex(out[0], out[1])
+
+
+def corr_current(ctx, H, J, psi_beta, D, dt, n_steps, cutoff=1e-10, tol=1e-14, mmax=40):
+    out = np.zeros(2 * (n_steps + 1))
+    ko = _abi._krylov(tol, mmax)
+    check(lib.ftd_corr_current(ctx.h, H.h, J.h, psi_beta.h, int(D), float(cutoff), float(dt),
+                               int(n_steps), C.byref(ko), _abi._dptr(out)))
+    return out[0::2] + 1j * out[1::2]
+
+
+def mobility(C_t, dt, beta, e0=1.0):
+    c = np.ascontiguousarray(np.asarray(C_t, dtype=np.complex128))
+    buf = np.empty(2 * c.size)
+    buf[0::2] = c.real
+    buf[1::2] = c.imag
+    mu, mu_cm = C.c_double(), C.c_double()
+    check(lib.ftd_mobility(_abi._dptr(buf), int(c.size), float(dt), float(beta), float(e0),
+                           C.byref(mu), C.byref(mu_cm)))
+    return mu.value, mu_cm.value
+
+
+def mps_from_host(ctx, tensors, log_norm=0.0, precision="c128"):
+    dims = []
+    flat = []
+    for t in tensors:
+        t = np.asarray(t, dtype=np.complex128)
+        dims += list(t.shape)
+        flat.append(t.reshape(-1))
+    x = np.concatenate(flat)
+    buf = np.empty(2 * x.size)
+    buf[0::2] = x.real
+    buf[1::2] = x.imag
+    d = np.asarray(dims, dtype=np.int32)
+    out = C.c_void_p()
+    check(lib.ftd_mps_from_host(ctx.h, len(tensors), d.ctypes.data_as(_abi.I32P),
+                                _abi._dptr(buf), float(log_norm), PRECISION[precision],
+                                C.byref(out)))
+    return Mps(ctx, out)
+
+
+def gemm(ctx, A, B, transA=0, transB=0, precision="c128"):
+    """C = op(A) op(B) on the device (kernel parity tests)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    B = np.ascontiguousarray(np.asarray(B, dtype=np.complex128))
+    M = A.shape[0] if transA == 0 else A.shape[1]
+    K = A.shape[1] if transA == 0 else A.shape[0]
+    N = B.shape[1] if transB == 0 else B.shape[0]
+    ab = np.empty(2 * A.size); ab[0::2] = A.real.reshape(-1); ab[1::2] = A.imag.reshape(-1)
+    bb = np.empty(2 * B.size); bb[0::2] = B.real.reshape(-1); bb[1::2] = B.imag.reshape(-1)
+    cb = np.zeros(2 * M * N)
+    check(lib.ftd_gemm(ctx.h, PRECISION[precision], M, N, K, int(transA), int(transB),
+                       _abi._dptr(ab), _abi._dptr(bb), _abi._dptr(cb)))
+    return (cb[0::2] + 1j * cb[1::2]).reshape(M, N)
+
+
+def heff_apply(ctx, H, psi, site, x, n_repeat=1):
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    xb = np.empty(2 * x.size)
+    xb[0::2] = x.real.reshape(-1)
+    xb[1::2] = x.imag.reshape(-1)
+    yb = np.zeros_like(xb)
+    check(lib.ftd_heff_apply(ctx.h, H.h, psi.h, int(site), _abi._dptr(xb), _abi._dptr(yb),
+                             int(n_repeat)))
+    return (yb[0::2] + 1j * yb[1::2]).reshape(x.shape)

@@ -1,0 +1,590 @@
+// C ABI of the library (see include/ftdmrg.h): argument checks, handle
+// ownership, status codes, and the drivers of the imaginary-time preparation
+// and the current correlation.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace ftd {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+template <typename F>
+static ftd_status guarded(F&& f) {
+    try {
+        f();
+        return FTD_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return FTD_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return FTD_EDEVICE;
+    } catch (...) {
+        set_error("unknown error");
+        return FTD_EDEVICE;
+    }
+}
+
+static void check_krylov(const ftd_krylov_opts* ko, double& tol, int& mmax) {
+    tol = ko ? ko->tol : 1e-14;
+    mmax = ko ? ko->mmax : 40;
+    FTD_CHECK(std::isfinite(tol) && tol > 0.0, FTD_EINVAL, "Krylov tolerance must be > 0");
+    FTD_CHECK(mmax >= 1 && mmax < kMaxKrylov, FTD_EINVAL, "Krylov mmax must be in [1, 63]");
+}
+
+static Prec to_prec(int32_t p) {
+    FTD_CHECK(p == FTD_C128 || p == FTD_C64 || p == FTD_BF16X3, FTD_EINVAL, "unknown precision");
+    return static_cast<Prec>(p);
+}
+
+// largest possible rank of every bond: min(prod_left d^2, prod_right d^2)
+static std::vector<double> max_bond(const Mps* psi) {
+    const int L = psi->L;
+    std::vector<double> out(std::max(0, L - 1));
+    std::vector<double> lp(L), rp(L);
+    double acc = 1.0;
+    for (int i = 0; i < L; ++i) {
+        acc = std::min(acc * psi->d[i] * psi->d[i], 1e18);
+        lp[i] = acc;
+    }
+    acc = 1.0;
+    for (int i = L - 1; i >= 0; --i) {
+        acc = std::min(acc * psi->d[i] * psi->d[i], 1e18);
+        rp[i] = acc;
+    }
+    for (int i = 0; i < L - 1; ++i) out[i] = std::min(lp[i], rp[i + 1]);
+    return out;
+}
+
+static Mps* taylor_growth(Ctx* ctx, const Mpo* H, const Mps* psi, double dtau, int D,
+                          double cutoff) {
+    Mps* phi = mps_clone(psi);
+    for (int k = 4; k >= 1; --k) {
+        Mps* Hphi = mpo_apply(ctx, H, phi);
+        mps_free(phi);
+        Mps* X = mps_add(ctx, psi, Hphi, cplx(-dtau / k, 0.0));
+        mps_free(Hphi);
+        phi = compress(ctx, X, D, cutoff, true);
+    }
+    return phi;
+}
+
+}  // namespace ftd
+
+using namespace ftd;
+
+extern "C" {
+
+const char* ftd_last_error(void) { return g_last_error.c_str(); }
+
+ftd_status ftd_ctx_create(int32_t device, void* hip_stream, const ftd_allocator* alloc,
+                          ftd_ctx** out) {
+    return guarded([&] {
+        FTD_CHECK(out != nullptr, FTD_EINVAL, "null output pointer");
+        int n = 0;
+        FTD_HIP(hipGetDeviceCount(&n));
+        FTD_CHECK(device >= 0 && device < n, FTD_EINVAL, "device index out of range");
+        FTD_HIP(hipSetDevice(device));
+        ftd_ctx* h = new ftd_ctx();
+        Ctx& c = h->c;
+        c.device = device;
+        c.stream = static_cast<hipStream_t>(hip_stream);
+        if (alloc && alloc->alloc && alloc->free) {
+            c.has_alloc = true;
+            c.alloc = *alloc;
+        }
+        try {
+            c.scal = static_cast<double*>(dev_alloc(&c, sizeof(double) * 4096));
+            c.iscal = static_cast<int*>(dev_alloc(&c, sizeof(int) * 64));
+            FTD_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_pinned_i), sizeof(int) * 64, hipHostMallocDefault));
+            FTD_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_pinned_d), sizeof(double) * 64, hipHostMallocDefault));
+            FTD_HIP(hipMemsetAsync(c.scal, 0, sizeof(double) * 4096, c.stream));
+            FTD_HIP(hipMemsetAsync(c.iscal, 0, sizeof(int) * 64, c.stream));
+            double* s = c.scal + 256;
+            c.kd.alpha = s;
+            c.kd.beta = s + kMaxKrylov;
+            c.kd.h = s + 2 * kMaxKrylov;
+            c.kd.u = s + 4 * kMaxKrylov + 2;
+            c.kd.nrm = s + 6 * kMaxKrylov + 4;
+            c.kd.flag = c.iscal + 32;
+            FTD_HIP(hipStreamSynchronize(c.stream));
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+void ftd_ctx_destroy(ftd_ctx* ctx) {
+    if (!ctx) return;
+    Ctx& c = ctx->c;
+    (void)hipStreamSynchronize(c.stream);
+    for (auto* b : {&c.ws_gemm_partial, &c.ws_red, &c.ws_T, &c.ws_U, &c.ws_X32, &c.ws_Y32,
+                    &c.ws_Krylov, &c.ws_tmp1, &c.ws_tmp2, &c.ws_tmp3, &c.ws_qr, &c.ws_svd1,
+                    &c.ws_svd2, &c.ws_svd3, &c.ws_site, &c.ws_perm, &c.ws_A32})
+        b->release(&c);
+    for (auto& b : c.envL) b.release(&c);
+    for (auto& b : c.envR) b.release(&c);
+    dev_free(&c, c.scal);
+    dev_free(&c, c.iscal);
+    if (c.h_pinned_i) (void)hipHostFree(c.h_pinned_i);
+    if (c.h_pinned_d) (void)hipHostFree(c.h_pinned_d);
+    for (auto e : c.event_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+ftd_status ftd_ctx_set_timing(ftd_ctx* ctx, int32_t enable) {
+    return guarded([&] {
+        FTD_CHECK(ctx, FTD_EINVAL, "null context");
+        ctx->c.timing = enable != 0;
+    });
+}
+
+ftd_status ftd_ctx_stats_reset(ftd_ctx* ctx) {
+    return guarded([&] {
+        FTD_CHECK(ctx, FTD_EINVAL, "null context");
+        FTD_HIP(hipStreamSynchronize(ctx->c.stream));
+        ctx->c.events.clear();
+        ctx->c.event_next = 0;
+        ctx->c.stats = ftd_stats{};
+    });
+}
+
+ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && out, FTD_EINVAL, "null argument");
+        Ctx& c = ctx->c;
+        FTD_HIP(hipStreamSynchronize(c.stream));
+        ftd_stats s = c.stats;
+        s.heff_launches = 0;
+        s.heff_ms = 0;
+        s.heff_flops = 0;
+        // per kernel identity totals
+        std::vector<double> kms(64, 0.0), kfl(64, 0.0), kby(64, 0.0);
+        std::vector<int64_t> kn(64, 0);
+        for (auto& e : c.events) {
+            float ms = 0.f;
+            FTD_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+            if (e.tag == TAG_HEFF || e.tag == TAG_KEFF) {
+                s.heff_launches++;
+                s.heff_ms += ms;
+                s.heff_flops += e.flops;
+            }
+            if (e.tag == TAG_HEFF) {
+                const int k = e.kind & 63;
+                kms[k] += ms;
+                kfl[k] += e.flops;
+                kby[k] += e.bytes;
+                kn[k]++;
+            }
+        }
+        int best = 0;
+        for (int k = 1; k < 64; ++k)
+            if (kms[k] > kms[best]) best = k;
+        s.dom_launches = kn[best];
+        s.dom_ms = kms[best];
+        s.dom_flops = kfl[best];
+        s.dom_bytes = kby[best];
+        *out = s;
+    });
+}
+
+ftd_status ftd_ctx_synchronize(ftd_ctx* ctx) {
+    return guarded([&] {
+        FTD_CHECK(ctx, FTD_EINVAL, "null context");
+        FTD_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+ftd_status ftd_mpo_build(ftd_ctx* ctx, const ftd_model* m, ftd_mpo** H, ftd_mpo** J) {
+    return guarded([&] {
+        FTD_CHECK(ctx && m && H && J, FTD_EINVAL, "null argument");
+        FTD_CHECK(m->n_mol >= (m->periodic ? 3 : 2), FTD_EINVAL,
+                  "need n_mol >= 3 on a ring (>= 2 open)");
+        FTD_CHECK(m->n_loc >= 0 && m->n_nl >= 0, FTD_EINVAL, "negative mode count");
+        FTD_CHECK(m->n_loc == 0 || m->levels_loc >= 1, FTD_EINVAL, "levels_loc < 1");
+        FTD_CHECK(m->n_nl == 0 || m->levels_nl >= 1, FTD_EINVAL, "levels_nl < 1");
+        FTD_CHECK(m->levels_loc <= 32 && m->levels_nl <= 32, FTD_EINVAL, "levels above 32");
+        FTD_CHECK(m->n_loc == 0 || (m->omega_loc && m->g_loc), FTD_EINVAL, "null local-mode arrays");
+        FTD_CHECK(m->n_nl == 0 || (m->omega_nl && m->g_nl), FTD_EINVAL, "null bond-mode arrays");
+        auto fin = [](double x) { return std::isfinite(x); };
+        FTD_CHECK(fin(m->V) && fin(m->R) && fin(m->e0), FTD_EINVAL, "non-finite V, R or e0");
+        for (int i = 0; i < m->n_loc; ++i)
+            FTD_CHECK(fin(m->omega_loc[i]) && fin(m->g_loc[i]), FTD_EINVAL, "non-finite local mode");
+        for (int i = 0; i < m->n_nl; ++i)
+            FTD_CHECK(fin(m->omega_nl[i]) && fin(m->g_nl[i]), FTD_EINVAL, "non-finite bond mode");
+        Ctx* c = &ctx->c;
+        Mpo* h = build_mpo(c, *m, false);
+        Mpo* j = nullptr;
+        try {
+            upload_mpo(c, h);
+            j = build_mpo(c, *m, true);
+            upload_mpo(c, j);
+        } catch (...) {
+            destroy_mpo(h);
+            destroy_mpo(j);
+            throw;
+        }
+        *H = new ftd_mpo{h};
+        *J = new ftd_mpo{j};
+    });
+}
+
+void ftd_mpo_destroy(ftd_mpo* mpo) {
+    if (!mpo) return;
+    (void)hipStreamSynchronize(mpo->m->ctx->stream);
+    destroy_mpo(mpo->m);
+    delete mpo;
+}
+
+ftd_status ftd_mpo_info(const ftd_mpo* mpo, int32_t* n_sites, int32_t* dims, int32_t* bond_w) {
+    return guarded([&] {
+        FTD_CHECK(mpo && n_sites, FTD_EINVAL, "null argument");
+        *n_sites = mpo->m->L;
+        for (int i = 0; i < mpo->m->L; ++i) {
+            if (dims) dims[i] = mpo->m->s[i].d;
+            if (bond_w && i < mpo->m->L - 1) bond_w[i] = mpo->m->s[i].wr;
+        }
+    });
+}
+
+void ftd_mps_destroy(ftd_mps* psi) {
+    if (!psi) return;
+    (void)hipStreamSynchronize(psi->m->ctx->stream);
+    mps_free(psi->m);
+    delete psi;
+}
+
+ftd_status ftd_mps_copy(ftd_ctx* ctx, const ftd_mps* src, ftd_mps** out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && src && out, FTD_EINVAL, "null argument");
+        *out = new ftd_mps{mps_clone(src->m)};
+    });
+}
+
+ftd_status ftd_mps_info(const ftd_mps* psi, int32_t* n_sites, int32_t* bond_dims,
+                        double* log_norm, int32_t* precision) {
+    return guarded([&] {
+        FTD_CHECK(psi, FTD_EINVAL, "null argument");
+        if (n_sites) *n_sites = psi->m->L;
+        if (bond_dims)
+            for (int i = 0; i < psi->m->L - 1; ++i) bond_dims[i] = psi->m->Dr[i];
+        if (log_norm) *log_norm = psi->m->log_norm;
+        if (precision) *precision = (int32_t)psi->m->prec;
+    });
+}
+
+ftd_status ftd_mps_get_site(ftd_ctx* ctx, const ftd_mps* psi, int32_t site, double* host,
+                            int64_t count) {
+    return guarded([&] {
+        FTD_CHECK(ctx && psi && host, FTD_EINVAL, "null argument");
+        const Mps* m = psi->m;
+        FTD_CHECK(site >= 0 && site < m->L, FTD_EINVAL, "site out of range");
+        const int64_t n = m->size(site);
+        FTD_CHECK(count >= n, FTD_EINVAL, "host buffer too small");
+        std::vector<double> tmp(2 * n);
+        FTD_HIP(hipMemcpyAsync(tmp.data(), m->A[site], sizeof(double) * 2 * n, hipMemcpyDeviceToHost,
+                               ctx->c.stream));
+        FTD_HIP(hipStreamSynchronize(ctx->c.stream));
+        for (int64_t k = 0; k < n; ++k) {
+            host[2 * k] = tmp[k];
+            host[2 * k + 1] = tmp[k + n];
+        }
+    });
+}
+
+ftd_status ftd_mps_from_host(ftd_ctx* ctx, int32_t n_sites, const int32_t* dims,
+                             const double* host, double log_norm, ftd_precision prec,
+                             ftd_mps** out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && dims && host && out && n_sites >= 1, FTD_EINVAL, "bad argument");
+        std::vector<int> Dl(n_sites), d(n_sites), Dr(n_sites);
+        for (int i = 0; i < n_sites; ++i) {
+            Dl[i] = dims[4 * i];
+            d[i] = dims[4 * i + 1];
+            FTD_CHECK(dims[4 * i + 2] == d[i], FTD_EINVAL, "P and Q legs must match");
+            Dr[i] = dims[4 * i + 3];
+            FTD_CHECK(Dl[i] >= 1 && d[i] >= 1 && Dr[i] >= 1, FTD_EINVAL, "bad site shape");
+            if (i > 0) FTD_CHECK(Dl[i] == Dr[i - 1], FTD_EINVAL, "bond dimensions do not chain");
+        }
+        FTD_CHECK(Dl[0] == 1 && Dr[n_sites - 1] == 1, FTD_EINVAL, "open boundary bonds must be 1");
+        Mps* m = mps_alloc(&ctx->c, Dl, d, Dr, to_prec(prec));
+        int64_t off = 0;
+        for (int i = 0; i < n_sites; ++i) {
+            const int64_t n = m->size(i);
+            std::vector<double> tmp(2 * n);
+            for (int64_t k = 0; k < n; ++k) {
+                tmp[k] = host[2 * (off + k)];
+                tmp[k + n] = host[2 * (off + k) + 1];
+            }
+            FTD_HIP(hipMemcpyAsync(m->A[i], tmp.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice,
+                                   ctx->c.stream));
+            FTD_HIP(hipStreamSynchronize(ctx->c.stream));
+            off += n;
+        }
+        m->log_norm = log_norm;
+        *out = new ftd_mps{m};
+    });
+}
+
+ftd_status ftd_mps_norm(ftd_ctx* ctx, const ftd_mps* psi, double* out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && psi && out, FTD_EINVAL, "null argument");
+        // <psi|psi> via the identity transfer: build a trivial MPO-free overlap
+        // by contracting bra and ket through the Q and P legs site by site.
+        const Mps* m = psi->m;
+        Ctx* c = &ctx->c;
+        DBuf E, F;
+        std::vector<double> one = {1.0, 0.0};
+        E.ensure(c, sizeof(double) * 2);
+        FTD_HIP(hipMemcpyAsync(E.p, one.data(), sizeof(double) * 2, hipMemcpyHostToDevice, c->stream));
+        for (int i = 0; i < m->L; ++i) {
+            const int Da = m->Dl[i], Db = m->Dr[i], dd = m->d[i] * m->d[i];
+            const int64_t n = m->size(i);
+            c->ws_site.ensure(c, sizeof(double) * 2 * n);
+            double* T = c->ws_site.as<double>();
+            GemmParams p{};
+            p.M = Da; p.N = dd * Db; p.K = Da;
+            p.sAm = Da; p.sAk = 1; p.planeA = (int64_t)Da * Da; p.a_kcontig = 1;
+            p.sBk = (int64_t)dd * Db; p.sBn = 1; p.planeB = n; p.b_kcontig = 0;
+            p.sCm = (int64_t)dd * Db; p.sCn = 1; p.planeC = n;
+            p.nprob = 1; p.prob[0].t1 = 1;
+            gemm(c, Prec::F64, true, E.p, m->A[i], T, p, TAG_NONE);
+            F.ensure(c, sizeof(double) * 2 * (size_t)Db * Db);
+            GemmParams q{};
+            q.M = Db; q.N = Db; q.K = Da * dd;
+            q.sAm = 1; q.sAk = Db; q.planeA = n; q.conjA = 1; q.a_kcontig = 0;
+            q.sBk = Db; q.sBn = 1; q.planeB = n; q.b_kcontig = 0;
+            q.sCm = Db; q.sCn = 1; q.planeC = (int64_t)Db * Db;
+            q.nprob = 1; q.prob[0].t1 = 1;
+            gemm(c, Prec::F64, true, m->A[i], T, F.p, q, TAG_NONE);
+            std::swap(E, F);
+        }
+        std::vector<double> h(2);
+        FTD_HIP(hipMemcpyAsync(h.data(), E.p, sizeof(double) * 2, hipMemcpyDeviceToHost, c->stream));
+        FTD_HIP(hipStreamSynchronize(c->stream));
+        E.release(c);
+        F.release(c);
+        *out = h[0];
+    });
+}
+
+ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t n_imag,
+                            int32_t n_grow, int32_t D, double cutoff, ftd_precision prec,
+                            const ftd_krylov_opts* ko, ftd_mps** psi_beta, double* log_Z) {
+    return guarded([&] {
+        FTD_CHECK(ctx && H && psi_beta && log_Z, FTD_EINVAL, "null argument");
+        FTD_CHECK(std::isfinite(beta) && beta >= 0.0, FTD_EINVAL, "beta must be >= 0");
+        FTD_CHECK(n_imag >= 1, FTD_EINVAL, "n_imag must be >= 1");
+        FTD_CHECK(D >= 1, FTD_EINVAL, "D must be >= 1");
+        FTD_CHECK(std::isfinite(cutoff) && cutoff >= 0.0 && cutoff < 1.0, FTD_EINVAL, "bad cutoff");
+        FTD_CHECK(n_grow <= n_imag, FTD_EINVAL, "n_grow > n_imag");
+        double tol;
+        int mmax;
+        check_krylov(ko, tol, mmax);
+        const Prec pr = to_prec(prec);
+        Ctx* c = &ctx->c;
+        const Mpo* h = H->m;
+        Mps* psi = identity_mps(c, h);
+        try {
+            Mps* t = compress(c, psi, D, cutoff, true);
+            psi = t;
+            mps_normalize(c, psi);
+            const double dtau = beta / (2.0 * n_imag);
+            int steps = 0;
+            const bool adaptive = n_grow < 0;
+            const int ng = adaptive ? n_imag : n_grow;
+            const std::vector<double> mb = max_bond(psi);
+            for (int s = 0; s < ng; ++s) {
+                std::vector<int> before(psi->Dr.begin(), psi->Dr.end() - 1);
+                Mps* nxt = taylor_growth(c, h, psi, dtau, D, cutoff);
+                mps_free(psi);
+                psi = nxt;
+                mps_normalize(c, psi);
+                ++steps;
+                if (adaptive) {
+                    bool all_full = true, grew = false;
+                    for (int i = 0; i < psi->L - 1; ++i) {
+                        if (psi->Dr[i] < std::min<double>(D, mb[i])) all_full = false;
+                        if (psi->Dr[i] > before[i]) grew = true;
+                    }
+                    if (all_full || !grew) break;
+                }
+            }
+            psi->prec = pr;
+            for (int s = steps; s < n_imag; ++s) {
+                tdvp_step(c, h, psi, cplx(-dtau, 0.0), tol, mmax);
+                mps_normalize(c, psi);
+            }
+        } catch (...) {
+            mps_free(psi);
+            throw;
+        }
+        *log_Z = 2.0 * psi->log_norm;
+        *psi_beta = new ftd_mps{psi};
+    });
+}
+
+ftd_status ftd_tdvp_step(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt_real,
+                         double dt_imag, const ftd_krylov_opts* ko) {
+    return guarded([&] {
+        FTD_CHECK(ctx && H && psi, FTD_EINVAL, "null argument");
+        FTD_CHECK(std::isfinite(dt_real) && std::isfinite(dt_imag), FTD_EINVAL, "non-finite step");
+        double tol;
+        int mmax;
+        check_krylov(ko, tol, mmax);
+        FTD_CHECK(H->m->L == psi->m->L, FTD_EINVAL, "MPO and MPS lengths differ");
+        tdvp_step(&ctx->c, H->m, psi->m, cplx(-dt_imag, -dt_real), tol, mmax);
+    });
+}
+
+ftd_status ftd_apply_compress(ftd_ctx* ctx, const ftd_mpo* O, const ftd_mps* psi, int32_t D,
+                              double cutoff, ftd_mps** out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && O && psi && out, FTD_EINVAL, "null argument");
+        FTD_CHECK(D >= 1, FTD_EINVAL, "D must be >= 1");
+        FTD_CHECK(O->m->L == psi->m->L, FTD_EINVAL, "MPO and MPS lengths differ");
+        Mps* r = apply_compress(&ctx->c, O->m, psi->m, D, cutoff);
+        r->prec = psi->m->prec;
+        *out = new ftd_mps{r};
+    });
+}
+
+ftd_status ftd_overlap(ftd_ctx* ctx, const ftd_mps* bra, const ftd_mpo* O, const ftd_mps* ket,
+                       double* out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && bra && O && ket && out, FTD_EINVAL, "null argument");
+        cplx v = overlap(&ctx->c, bra->m, O->m, ket->m);
+        out[0] = v.real();
+        out[1] = v.imag();
+    });
+}
+
+ftd_status ftd_corr_current(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mpo* J,
+                            const ftd_mps* psi_beta, int32_t D, double cutoff, double dt,
+                            int32_t n_steps, const ftd_krylov_opts* ko, double* C_out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && H && J && psi_beta && C_out, FTD_EINVAL, "null argument");
+        FTD_CHECK(n_steps >= 0 && D >= 1 && std::isfinite(dt), FTD_EINVAL, "bad run arguments");
+        double tol;
+        int mmax;
+        check_krylov(ko, tol, mmax);
+        Ctx* c = &ctx->c;
+        Mps* psi = mps_clone(psi_beta->m);
+        Mps* phi = nullptr;
+        try {
+            psi->log_norm = 0.0;
+            phi = apply_compress(c, J->m, psi, D, cutoff);
+            phi->prec = psi->prec;
+            phi->log_norm = 0.0;
+            cplx c0 = overlap(c, psi, J->m, phi);
+            C_out[0] = c0.real();
+            C_out[1] = c0.imag();
+            for (int k = 1; k <= n_steps; ++k) {
+                tdvp_step(c, H->m, psi, cplx(0.0, -dt), tol, mmax);
+                tdvp_step(c, H->m, phi, cplx(0.0, -dt), tol, mmax);
+                cplx ck = overlap(c, psi, J->m, phi);
+                C_out[2 * k] = ck.real();
+                C_out[2 * k + 1] = ck.imag();
+            }
+        } catch (...) {
+            mps_free(psi);
+            mps_free(phi);
+            throw;
+        }
+        mps_free(psi);
+        mps_free(phi);
+    });
+}
+
+ftd_status ftd_mobility(const double* C, int32_t n, double dt, double beta, double e0,
+                        double* mu_au, double* mu_cm2Vs) {
+    return guarded([&] {
+        FTD_CHECK(C && mu_au && mu_cm2Vs, FTD_EINVAL, "null argument");
+        FTD_CHECK(n >= 2, FTD_EINVAL, "need at least two samples");
+        FTD_CHECK(dt > 0.0 && beta >= 0.0 && e0 != 0.0, FTD_EINVAL, "bad dt, beta or e0");
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double w = (k == 0 || k == n - 1) ? 0.5 : 1.0;
+            s += w * C[2 * k];
+        }
+        const double mu = beta / e0 * dt * s;
+        // e a0^2 / hbar in cm^2/(V s), CODATA 2018
+        const double e = 1.602176634e-19, a0 = 5.29177210903e-11, hbar = 1.054571817e-34;
+        *mu_au = mu;
+        *mu_cm2Vs = mu * e * a0 * a0 / hbar * 1e4;
+    });
+}
+
+ftd_status ftd_heff_apply(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, int32_t site,
+                          const double* x, double* y, int32_t n_repeat) {
+    return guarded([&] {
+        FTD_CHECK(ctx && H && psi && x && y, FTD_EINVAL, "null argument");
+        heff_apply_host(&ctx->c, H->m, psi->m, site, x, y, n_repeat);
+    });
+}
+
+ftd_status ftd_gemm(ftd_ctx* ctx, int32_t precision, int32_t M, int32_t N, int32_t K,
+                    int32_t transA, int32_t transB, const double* A, const double* B, double* C) {
+    return guarded([&] {
+        FTD_CHECK(ctx && A && B && C, FTD_EINVAL, "null argument");
+        FTD_CHECK(M >= 1 && N >= 1 && K >= 1, FTD_EINVAL, "empty GEMM");
+        FTD_CHECK(transA >= 0 && transA <= 2 && transB >= 0 && transB <= 2, FTD_EINVAL, "bad trans");
+        const Prec pr = to_prec(precision);
+        FTD_CHECK(pr != Prec::BF16X3, FTD_EINVAL, "ftd_gemm: c128 or c64 only");
+        Ctx* c = &ctx->c;
+        const int64_t na = (int64_t)M * K, nb = (int64_t)K * N, nc = (int64_t)M * N;
+        const size_t es = pr == Prec::F64 ? 8 : 4;
+        void* dA = dev_alloc(c, es * 2 * na);
+        void* dB = dev_alloc(c, es * 2 * nb);
+        double* dC = static_cast<double*>(dev_alloc(c, 8 * 2 * nc));
+        auto up = [&](const double* h, void* d, int64_t n) {
+            if (pr == Prec::F64) {
+                std::vector<double> t(2 * n);
+                for (int64_t k = 0; k < n; ++k) {
+                    t[k] = h[2 * k];
+                    t[k + n] = h[2 * k + 1];
+                }
+                FTD_HIP(hipMemcpy(d, t.data(), 8 * 2 * n, hipMemcpyHostToDevice));
+            } else {
+                std::vector<float> t(2 * n);
+                for (int64_t k = 0; k < n; ++k) {
+                    t[k] = (float)h[2 * k];
+                    t[k + n] = (float)h[2 * k + 1];
+                }
+                FTD_HIP(hipMemcpy(d, t.data(), 4 * 2 * n, hipMemcpyHostToDevice));
+            }
+        };
+        up(A, dA, na);
+        up(B, dB, nb);
+        GemmParams p{};
+        p.M = M; p.N = N; p.K = K;
+        if (transA == 0) { p.sAm = K; p.sAk = 1; p.a_kcontig = 1; }
+        else { p.sAm = 1; p.sAk = M; p.a_kcontig = 0; p.conjA = transA == 2; }
+        if (transB == 0) { p.sBk = N; p.sBn = 1; p.b_kcontig = 0; }
+        else { p.sBk = 1; p.sBn = K; p.b_kcontig = 1; p.conjB = transB == 2; }
+        p.planeA = na; p.planeB = nb;
+        p.sCm = N; p.sCn = 1; p.planeC = nc;
+        p.nprob = 1; p.prob[0].t1 = 1;
+        gemm(c, pr, true, dA, dB, dC, p, TAG_NONE);
+        std::vector<double> t(2 * nc);
+        FTD_HIP(hipMemcpyAsync(t.data(), dC, 8 * 2 * nc, hipMemcpyDeviceToHost, c->stream));
+        FTD_HIP(hipStreamSynchronize(c->stream));
+        for (int64_t k = 0; k < nc; ++k) {
+            C[2 * k] = t[k];
+            C[2 * k + 1] = t[k + nc];
+        }
+        dev_free(c, dA);
+        dev_free(c, dB);
+        dev_free(c, dC);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,280 @@
+// Internal declarations shared by the ftdmrg host driver and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ftdmrg.h"
+
+namespace ftd {
+
+using cplx = std::complex<double>;
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+
+struct Error {
+    ftd_status code;
+    std::string msg;
+};
+
+#define FTD_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::ftd::Error{FTD_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define FTD_CHECK(cond, code, msg)                                                      \
+    do {                                                                                \
+        if (!(cond)) throw ::ftd::Error{code, msg};                                     \
+    } while (0)
+
+// --------------------------------------------------------------- constants
+constexpr int kMaxTerms = 32;   // summed GEMM products across all problems
+constexpr int kMaxProbs = 16;   // independent GEMM outputs per launch
+constexpr int kMaxMixJobs = 16;
+constexpr int kMaxMixEnts = 40;
+constexpr int kMaxKrylov = 64;  // one wavefront holds the tridiagonal problem
+
+// ------------------------------------------------------------------ buffers
+struct Ctx;
+
+// Device allocation through the context allocator.
+void* dev_alloc(Ctx* ctx, size_t bytes);
+void dev_free(Ctx* ctx, void* p);
+
+// A growable device buffer.  Growth synchronises the context stream before the
+// old block is released, so kernels still queued on it never see freed memory.
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void ensure(Ctx* ctx, size_t need);
+    void release(Ctx* ctx);
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------- GEMM API
+// C_p = sum over terms t of problem p of opA(A + offA_t) * opB(B + offB_t)
+// Complex operands in split planes: the imaginary plane of operand X starts
+// `planeX` elements after its real plane.  Element (m,k) of A sits at
+// m*sAm + k*sAk; (k,n) of B at k*sBk + n*sBn; (m,n) of C at m*sCm + n*sCn.
+struct GemmTerm {
+    int64_t offA, offB;
+};
+struct GemmProb {
+    int64_t offC;
+    int t0, t1;  // term range
+};
+struct GemmParams {
+    int M, N, K;
+    int64_t sAm, sAk, sBk, sBn, sCm, sCn;
+    int64_t planeA, planeB, planeC;
+    int conjA, conjB, accumulate;
+    int nprob, ksplit;
+    int a_kcontig, b_kcontig;
+    GemmProb prob[kMaxProbs];
+    GemmTerm term[kMaxTerms];
+};
+
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
+
+// kind tags used for timing attribution
+enum KernelTag { TAG_NONE = 0, TAG_HEFF = 1, TAG_KEFF = 2 };
+
+// Launch a complex GEMM.  Tin/Tout: double/double, float/float, float/double.
+void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void* C,
+          GemmParams p, int tag);
+
+// ---------------------------------------------------------- channel mixing
+// out_j[a][p'][q][b] (+)= sum_e op_e[p'][p] in_e[a][p][q][b]
+struct MixJob {
+    int64_t offOut;
+    int e0, e1;
+};
+struct MixEnt {
+    int64_t offIn;
+    int op;
+};
+struct MixParams {
+    int Da, d, Db;
+    int64_t planeIn, planeOut;
+    int64_t opStride;   // elements per op (re plane then im plane, d*d each)
+    int accumulate;
+    int njobs;
+    MixJob job[kMaxMixJobs];
+    MixEnt ent[kMaxMixEnts];
+};
+void chanmix(Ctx* ctx, Prec prec, bool out_f64, const void* in, const void* ops, void* out,
+             const MixParams& p);
+
+// ----------------------------------------------------------- vector kernels
+void k_copy_f64(Ctx* ctx, const double* src, double* dst, int64_t n);
+void k_convert_f64_f32(Ctx* ctx, const double* src, float* dst, int64_t n);
+void k_scale_cplx(Ctx* ctx, double* x, int64_t n, int64_t plane, double re, double im);
+void k_scale_by_dev(Ctx* ctx, double* x, int64_t n, int64_t plane, const double* s, int inv);
+void k_zero(Ctx* ctx, void* p, size_t bytes);
+// partial sums for <x,y> (complex) and |x|^2; result into dev out[0..1]
+void k_dot(Ctx* ctx, const double* x, const double* y, int64_t n, int64_t plane, double* out);
+void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out);
+// h[j] = <V_j, w>, j < k; V_j at V + j*vstride
+void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double* w, int64_t n,
+                int64_t plane, double* h);
+// w -= sum_j V_j h[j]
+void k_multiaxpy(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h, double* w,
+                 int64_t n, int64_t plane);
+// y = scale * sum_j V_j u[j]
+void k_lincomb(Ctx* ctx, const double* V, int64_t vstride, int k, const double* u,
+               const double* scale_dev, double* y, int64_t n, int64_t plane);
+// embed src[Da][dd][Db] into dst[DA][dd][DB] at (a0, b0), times (re, im)
+void k_embed(Ctx* ctx, const double* src, int Da, int dd, int Db, double* dst, int DA, int DB,
+             int a0, int b0, double re, double im);
+// exact MPO x MPS site product
+struct ApplyEnt {
+    int cl, cr, op;
+};
+void k_mpo_apply(Ctx* ctx, const double* A, int Da, int d, int Db, const double* ops,
+                 int64_t opStride, int wl, int wr, const ApplyEnt* ents_dev, int nents,
+                 double* B);
+// B[a][b] planar -> A: dst = src row-major (rows x cols) transposed, with conj
+void k_transpose(Ctx* ctx, const double* src, int64_t rows, int64_t cols, int64_t splane,
+                 double* dst, int64_t dplane, int conj);
+
+// ------------------------------------------------------------- Krylov tail
+// Device state of one Lanczos run.
+struct KrylovDev {
+    double* alpha;   // [kMaxKrylov]
+    double* beta;    // [kMaxKrylov]
+    double* h;       // complex [2*(kMaxKrylov+1)]
+    double* u;       // complex [2*kMaxKrylov]
+    double* nrm;     // [4]
+    int* flag;       // [4]: converged, k, failed
+};
+void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
+                    int exhausted);
+void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane);
+void k_set_alpha(Ctx* ctx, KrylovDev kd, int k);
+
+// ----------------------------------------------------------------- QR / SVD
+// Shifted CholeskyQR (three passes) of a full-column-rank M (m x n, row-major,
+// split planes).  Q overwrites M; R (n x n upper, row-major, planar) returned.
+void qr_chol(Ctx* ctx, double* M, int64_t m, int64_t n, double* R);
+// LQ of a full-row-rank M (n x m row-major): M = L Q, Q overwrites M, L n x n.
+void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L);
+// Householder QR for any rank (m x n row-major, m >= 1): Q (m x r) and R
+// (r x n), r = min(m, n), diag(R) real >= 0.
+void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, double* R);
+// Thin SVD of X (m x n, row-major, m >= n) by one-sided Jacobi:
+// X = U S V^H, U m x n (columns scaled), S[n] sorted descending, V n x n.
+void svd_jacobi(Ctx* ctx, const double* X, int64_t m, int64_t n, double* U, double* S,
+                double* V);
+
+// ----------------------------------------------------------------- objects
+struct MpoEntry {
+    int cl, cr;
+    bool identity;
+    std::vector<cplx> op;  // d x d, row-major [out][in], coefficient folded in
+};
+struct MpoSite {
+    int d = 0, wl = 0, wr = 0;
+    int idxI_l = -1, idxF_l = -1, idxI_r = -1, idxF_r = -1;
+    std::vector<MpoEntry> ents;
+    double* ops64 = nullptr;    // [nents][2][d][d]
+    float* ops32 = nullptr;
+    ApplyEnt* apply_ents = nullptr;  // device copy of (cl, cr, op)
+};
+struct Mpo {
+    Ctx* ctx = nullptr;
+    int L = 0;
+    std::vector<MpoSite> s;
+    std::vector<int> electronic;   // 1 where the site is a molecule's carrier site
+    int wmax = 0, dmax = 0;
+};
+
+struct Mps {
+    Ctx* ctx = nullptr;
+    int L = 0;
+    std::vector<int> Dl, Dr, d;
+    std::vector<double*> A;   // planar complex, n = Dl*d*d*Dr per plane
+    double log_norm = 0.0;
+    Prec prec = Prec::F64;
+    int64_t size(int i) const { return (int64_t)Dl[i] * d[i] * d[i] * Dr[i]; }
+};
+
+struct EventPair {
+    hipEvent_t a, b;
+    double flops, bytes;
+    int tag;
+    int kind;   // kernel identity for dominant-kernel attribution
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool has_alloc = false;
+    ftd_allocator alloc{};
+    // timing
+    bool timing = false;
+    std::vector<EventPair> events;
+    std::vector<hipEvent_t> event_pool;
+    size_t event_next = 0;
+    ftd_stats stats{};
+    // scratch
+    DBuf ws_gemm_partial, ws_red;
+    DBuf ws_T, ws_U, ws_X32, ws_Y32, ws_Krylov, ws_tmp1, ws_tmp2, ws_tmp3, ws_qr;
+    DBuf ws_svd1, ws_svd2, ws_svd3, ws_site, ws_perm;
+    // environments of the current sweep: envL[i] left of site i, envR[i]
+    // right of site i-1 (i.e. contraction of sites i..L-1)
+    std::vector<DBuf> envL, envR;
+    std::vector<int> envL_w, envR_w, envL_D, envR_D;
+    DBuf ws_A32;
+    double* scal = nullptr;       // device scalars (Krylov state etc.)
+    int* iscal = nullptr;
+    int* h_pinned_i = nullptr;    // host pinned readback
+    double* h_pinned_d = nullptr;
+    KrylovDev kd{};
+};
+
+hipEvent_t timing_event(Ctx* ctx);
+void record_kernel(Ctx* ctx, hipEvent_t a, hipEvent_t b, double flops, double bytes, int tag,
+                   int kind);
+
+// ---------------------------------------------------------- high level ops
+Mpo* build_mpo(Ctx* ctx, const ftd_model& m, bool current);
+void upload_mpo(Ctx* ctx, Mpo* mpo);
+void destroy_mpo(Mpo* mpo);
+
+Mps* mps_alloc(Ctx* ctx, const std::vector<int>& Dl, const std::vector<int>& d,
+               const std::vector<int>& Dr, Prec prec);
+void mps_free(Mps* m);
+Mps* mps_clone(const Mps* m);
+Mps* identity_mps(Ctx* ctx, const Mpo* H);
+
+void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax);
+Mps* apply_compress(Ctx* ctx, const Mpo* O, const Mps* psi, int D, double cutoff);
+Mps* compress(Ctx* ctx, Mps* X, int D, double cutoff, bool consume);
+Mps* mps_add(Ctx* ctx, const Mps* a, const Mps* b, cplx c);
+Mps* mpo_apply(Ctx* ctx, const Mpo* O, const Mps* psi);
+double mps_normalize(Ctx* ctx, Mps* psi);
+cplx overlap(Ctx* ctx, const Mps* bra, const Mpo* O, const Mps* ket);
+void heff_apply_host(Ctx* ctx, const Mpo* H, const Mps* psi, int site, const double* x,
+                     double* y, int nrep);
+
+}  // namespace ftd
+
+struct ftd_ctx {
+    ftd::Ctx c;
+};
+struct ftd_mpo {
+    ftd::Mpo* m;
+};
+struct ftd_mps {
+    ftd::Mps* m;
+};

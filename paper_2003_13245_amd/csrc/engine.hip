@@ -1,0 +1,1070 @@
+// Host driver of the hot path: environments, effective Hamiltonians, the
+// Krylov exponential, one-site projector-splitting sweeps, compression,
+// imaginary-time preparation and the current correlation.
+//
+// Every floating-point step runs in HIP kernels; the host only orders
+// launches, reads back Krylov stop flags and truncation spectra, and keeps
+// shapes.  Site tensors A[a][p][q][b] are float64 complex in split planes
+// (real plane, then imaginary plane).  Environments hold one D x D block per
+// MPO channel, each block [re plane][im plane].
+#include <algorithm>
+#include <functional>
+#include <numeric>
+
+#include "common.h"
+
+namespace ftd {
+
+// ================================================================ buffers
+void* dev_alloc(Ctx* ctx, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (ctx->has_alloc) {
+        p = ctx->alloc.alloc(bytes, ctx->alloc.user);
+        FTD_CHECK(p != nullptr, FTD_ENOMEM, "allocator callback failed");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        FTD_CHECK(e == hipSuccess, FTD_ENOMEM, "hipMalloc failed");
+    }
+    return p;
+}
+void dev_free(Ctx* ctx, void* p) {
+    if (!p) return;
+    if (ctx->has_alloc)
+        ctx->alloc.free(p, ctx->alloc.user);
+    else
+        (void)hipFree(p);
+}
+void DBuf::ensure(Ctx* ctx, size_t need) {
+    if (need <= bytes) return;
+    if (p) {
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+        dev_free(ctx, p);
+        p = nullptr;
+        bytes = 0;
+    }
+    size_t want = need + need / 4 + 256;
+    p = dev_alloc(ctx, want);
+    bytes = want;
+}
+void DBuf::release(Ctx* ctx) {
+    dev_free(ctx, p);
+    p = nullptr;
+    bytes = 0;
+}
+
+hipEvent_t timing_event(Ctx* ctx) {
+    if (ctx->event_next >= ctx->event_pool.size()) {
+        hipEvent_t e;
+        FTD_HIP(hipEventCreate(&e));
+        ctx->event_pool.push_back(e);
+    }
+    return ctx->event_pool[ctx->event_next++];
+}
+void record_kernel(Ctx* ctx, hipEvent_t a, hipEvent_t b, double flops, double bytes, int tag,
+                   int kind) {
+    ctx->events.push_back({a, b, flops, bytes, tag, kind});
+}
+
+// ============================================================ small kernels
+__global__ void eye_f64_kernel(double* X, int n, int64_t plane) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        X[e] = (e / n == e % n) ? 1.0 : 0.0;
+        X[e + plane] = 0.0;
+    }
+}
+__global__ void eye_f32_kernel(float* X, int n, int64_t plane) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        X[e] = (e / n == e % n) ? 1.0f : 0.0f;
+        X[e + plane] = 0.0f;
+    }
+}
+// dst[:, j] = s_j * op(src[:, perm[j]])  (column-major, m rows)
+__global__ void gather_cols_kernel(const double* __restrict__ src, int64_t m, int64_t splane,
+                                   const int* __restrict__ perm, const double* __restrict__ sc,
+                                   int k, int conj, double* __restrict__ dst, int64_t dplane) {
+    const int64_t tot = m * k;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / m);
+        const int64_t i = e % m;
+        const double s = sc ? sc[j] : 1.0;
+        const int64_t o = (int64_t)perm[j] * m + i;
+        dst[e] = s * src[o];
+        dst[e + dplane] = (conj ? -s : s) * src[o + splane];
+    }
+}
+
+static dim3 gr(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 65535 * 4) b = 65535 * 4;
+    return dim3((unsigned)b);
+}
+static void eye(Ctx* ctx, void* X, int n, int64_t plane, bool f32) {
+    if (f32)
+        eye_f32_kernel<<<gr((int64_t)n * n), 256, 0, ctx->stream>>>(static_cast<float*>(X), n, plane);
+    else
+        eye_f64_kernel<<<gr((int64_t)n * n), 256, 0, ctx->stream>>>(static_cast<double*>(X), n, plane);
+    FTD_HIP(hipGetLastError());
+}
+
+// ===================================================================== MPS
+Mps* mps_alloc(Ctx* ctx, const std::vector<int>& Dl, const std::vector<int>& d,
+               const std::vector<int>& Dr, Prec prec) {
+    Mps* m = new Mps();
+    m->ctx = ctx;
+    m->L = (int)d.size();
+    m->Dl = Dl;
+    m->Dr = Dr;
+    m->d = d;
+    m->prec = prec;
+    m->A.assign(m->L, nullptr);
+    try {
+        for (int i = 0; i < m->L; ++i)
+            m->A[i] = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m->size(i)));
+    } catch (...) {
+        mps_free(m);
+        throw;
+    }
+    return m;
+}
+void mps_free(Mps* m) {
+    if (!m) return;
+    (void)hipStreamSynchronize(m->ctx->stream);
+    for (auto p : m->A) dev_free(m->ctx, p);
+    delete m;
+}
+Mps* mps_clone(const Mps* s) {
+    Mps* m = mps_alloc(s->ctx, s->Dl, s->d, s->Dr, s->prec);
+    for (int i = 0; i < s->L; ++i) k_copy_f64(s->ctx, s->A[i], m->A[i], 2 * s->size(i));
+    m->log_norm = s->log_norm;
+    return m;
+}
+static void set_site(Ctx* ctx, Mps* m, int i, int Dl, int Dr, double* buf) {
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, m->A[i]);
+    m->A[i] = buf;
+    m->Dl[i] = Dl;
+    m->Dr[i] = Dr;
+}
+
+// The purified identity of the one-carrier space, |I> = sum_i |i>_P |i>_Q.
+// Bond states: "carrier not yet placed" and "placed"; electronic sites move
+// between them with p = q = 1, phonon sites carry the identity on (p, q).
+Mps* identity_mps(Ctx* ctx, const Mpo* H) {
+    const int L = H->L;
+    std::vector<int> d(L), kind(L);
+    std::vector<int> epos;
+    for (int i = 0; i < L; ++i) {
+        d[i] = H->s[i].d;
+        kind[i] = H->electronic[i];
+        if (kind[i]) epos.push_back(i);
+    }
+    FTD_CHECK(!epos.empty(), FTD_EINVAL, "MPO has no carrier sites");
+    const int fe = epos.front(), le = epos.back();
+    std::vector<int> Dl(L), Dr(L);
+    for (int i = 0; i < L; ++i) {
+        Dl[i] = (i <= fe || i > le) ? 1 : 2;
+        Dr[i] = (i < fe || i >= le) ? 1 : 2;
+    }
+    Mps* m = mps_alloc(ctx, Dl, d, Dr, Prec::F64);
+    double dim = (double)epos.size();
+    for (int i = 0; i < L; ++i)
+        if (!kind[i]) dim *= d[i];
+    for (int i = 0; i < L; ++i) {
+        const int64_t n = m->size(i);
+        std::vector<double> h(2 * n, 0.0);
+        const int dd = d[i];
+        auto at = [&](int a, int p, int q, int b) -> double& {
+            return h[(((int64_t)a * dd + p) * dd + q) * Dr[i] + b];
+        };
+        // bond labels: 0 none, 1 placed
+        auto lab_l = [&](int a) { return (i <= fe) ? 0 : (i > le ? 1 : a); };
+        auto lab_r = [&](int b) { return (i < fe) ? 0 : (i >= le ? 1 : b); };
+        for (int a = 0; a < Dl[i]; ++a)
+            for (int b = 0; b < Dr[i]; ++b) {
+                const int la = lab_l(a), lb = lab_r(b);
+                if (kind[i]) {
+                    if (la == 0 && lb == 0) at(a, 0, 0, b) = 1.0;
+                    if (la == 0 && lb == 1) at(a, 1, 1, b) = 1.0;
+                    if (la == 1 && lb == 1) at(a, 0, 0, b) = 1.0;
+                } else if (la == lb) {
+                    for (int v = 0; v < dd; ++v) at(a, v, v, b) = 1.0;
+                }
+            }
+        if (i == 0)
+            for (auto& x : h) x /= std::sqrt(dim);
+        FTD_HIP(hipMemcpyAsync(m->A[i], h.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice,
+                               ctx->stream));
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    m->log_norm = 0.5 * std::log(dim);
+    return m;
+}
+
+static double read_scalar(Ctx* ctx, const double* dev) {
+    FTD_HIP(hipMemcpyAsync(ctx->h_pinned_d, dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
+    return ctx->h_pinned_d[0];
+}
+
+double mps_normalize(Ctx* ctx, Mps* psi) {
+    const int64_t n = psi->size(0);
+    k_nrm2(ctx, psi->A[0], n, n, ctx->scal + 4);
+    const double nn = read_scalar(ctx, ctx->scal + 4);
+    FTD_CHECK(std::isfinite(nn) && nn > 0.0, FTD_ENOCONV, "state norm is zero or not finite");
+    const double nrm = std::sqrt(nn);
+    k_scale_cplx(ctx, psi->A[0], n, n, 1.0 / nrm, 0.0);
+    psi->log_norm += std::log(nrm);
+    return nrm;
+}
+
+// ============================================================ environments
+struct EnvView {
+    void* p;      // channel c block at p + c*2*D1*D2 (element type by precision)
+    int w, D1, D2;
+};
+
+static size_t esz(Prec prec) { return prec == Prec::F64 ? sizeof(double) : sizeof(float); }
+
+static EnvView env_get(Ctx* ctx, std::vector<DBuf>& bufs, std::vector<int>& ws,
+                       std::vector<int>& Ds, int i, int w, int D, Prec prec) {
+    if ((int)bufs.size() <= i) {
+        bufs.resize(i + 1);
+        ws.resize(i + 1, 0);
+        Ds.resize(i + 1, 0);
+    }
+    bufs[i].ensure(ctx, esz(prec) * 2 * (size_t)w * D * D);
+    ws[i] = w;
+    Ds[i] = D;
+    return {bufs[i].p, w, D, D};
+}
+
+static void boundary_env(Ctx* ctx, EnvView e, Prec prec) {
+    eye(ctx, e.p, 1, 1, prec != Prec::F64);
+}
+
+// compute-precision copy of a site tensor into slot `slot` of ws_T
+static void load_slot(Ctx* ctx, Prec prec, const double* x, int64_t n, void* Tbase, int slot) {
+    if (prec == Prec::F64)
+        k_copy_f64(ctx, x, static_cast<double*>(Tbase) + (int64_t)slot * 2 * n, 2 * n);
+    else
+        k_convert_f64_f32(ctx, x, static_cast<float*>(Tbase) + (int64_t)slot * 2 * n, 2 * n);
+}
+
+static const void* ops_of(const MpoSite& W, Prec prec) {
+    return prec == Prec::F64 ? (const void*)W.ops64 : (const void*)W.ops32;
+}
+
+// Stage 1: T[c] = E[c] * X for the listed channels (batched GEMM).
+// X lives in slot xs of Tbase; T[c] in slot c.  Shapes: E[c] Da1 x Da2,
+// X Da2 x (dd * Db), T Da1 x (dd * Db).
+static void stage_left(Ctx* ctx, Prec prec, const EnvView& E, const std::vector<int>& chans,
+                       void* Tbase, int xs, int Da1, int Da2, int dd, int Db, int64_t nslot,
+                       int tag) {
+    if (chans.empty()) return;
+    const int64_t nX = (int64_t)Da2 * dd * Db;
+    for (size_t c0 = 0; c0 < chans.size(); c0 += kMaxProbs) {
+        GemmParams p{};
+        p.M = Da1;
+        p.N = dd * Db;
+        p.K = Da2;
+        p.sAm = Da2; p.sAk = 1; p.planeA = (int64_t)Da1 * Da2; p.a_kcontig = 1;
+        p.sBk = (int64_t)dd * Db; p.sBn = 1; p.planeB = nX; p.b_kcontig = 0;
+        p.sCm = (int64_t)dd * Db; p.sCn = 1; p.planeC = nslot;
+        const size_t c1 = std::min(chans.size(), c0 + kMaxProbs);
+        p.nprob = (int)(c1 - c0);
+        for (size_t k = c0; k < c1; ++k) {
+            const int c = chans[k];
+            const int j = (int)(k - c0);
+            p.prob[j].offC = (int64_t)c * 2 * nslot;
+            p.prob[j].t0 = j;
+            p.prob[j].t1 = j + 1;
+            p.term[j].offA = (int64_t)c * 2 * Da1 * Da2;
+            p.term[j].offB = (int64_t)xs * 2 * nslot;
+        }
+        gemm(ctx, prec, prec == Prec::F64, E.p, Tbase, Tbase, p, tag);
+    }
+}
+
+// Stage 2 plan: for each output channel, entries (input slot, op).  Returns
+// for every output channel the slot that holds its mixed tensor (alias when
+// the column is a single identity entry).
+struct MixPlan {
+    std::vector<int> out_slot;       // per output channel, -1 if column empty
+};
+
+// by_col: entries grouped by output channel; each entry (input channel, op)
+static MixPlan stage_mix(Ctx* ctx, Prec prec, const MpoSite& W, bool left_to_right,
+                         const std::vector<int>& in_slot, int n_out, int out_base,
+                         const std::vector<int>& skip_out, void* Tbase, int Da, int d, int Db,
+                         int64_t nslot, int direct_out, void* direct_ptr, bool direct_f64,
+                         bool direct_acc) {
+    MixPlan plan;
+    plan.out_slot.assign(n_out, -1);
+    std::vector<std::vector<std::pair<int, int>>> col(n_out);
+    for (size_t e = 0; e < W.ents.size(); ++e) {
+        const int o = left_to_right ? W.ents[e].cr : W.ents[e].cl;
+        const int i = left_to_right ? W.ents[e].cl : W.ents[e].cr;
+        col[o].push_back({i, (int)e});
+    }
+    MixParams mp{};
+    mp.Da = Da;
+    mp.d = d;
+    mp.Db = Db;
+    mp.planeIn = nslot;
+    mp.planeOut = nslot;
+    mp.opStride = 2 * (int64_t)d * d;
+    MixParams md = mp;
+    int ne = 0, ned = 0;
+    for (int o = 0; o < n_out; ++o) {
+        if (col[o].empty()) continue;
+        if (std::find(skip_out.begin(), skip_out.end(), o) != skip_out.end()) continue;
+        if (o == direct_out) {
+            md.job[md.njobs] = {0, ned, ned + (int)col[o].size()};
+            for (auto& pr : col[o]) md.ent[ned++] = {(int64_t)in_slot[pr.first] * 2 * nslot, pr.second};
+            md.njobs++;
+            continue;
+        }
+        if (col[o].size() == 1 && W.ents[col[o][0].second].identity) {
+            plan.out_slot[o] = in_slot[col[o][0].first];
+            continue;
+        }
+        const int slot = out_base + o;
+        FTD_CHECK(mp.njobs < kMaxMixJobs && ne + (int)col[o].size() <= kMaxMixEnts, FTD_EINVAL,
+                  "MPO site too wide for the channel mixer");
+        mp.job[mp.njobs] = {(int64_t)slot * 2 * nslot, ne, ne + (int)col[o].size()};
+        for (auto& pr : col[o]) mp.ent[ne++] = {(int64_t)in_slot[pr.first] * 2 * nslot, pr.second};
+        mp.njobs++;
+        plan.out_slot[o] = slot;
+    }
+    if (mp.njobs) chanmix(ctx, prec, false, Tbase, ops_of(W, prec), Tbase, mp);
+    if (md.njobs) {
+        md.planeOut = nslot;
+        md.accumulate = direct_acc ? 1 : 0;
+        chanmix(ctx, prec, direct_f64, Tbase, ops_of(W, prec), direct_ptr, md);
+    }
+    return plan;
+}
+
+// y = H_eff x at a site with left env L (channels W.wl, Da x Da) and right
+// env R (channels W.wr, Db x Db).  Canonical gauge: L[I] = 1, R[F] = 1.
+static void heff(Ctx* ctx, Prec prec, const MpoSite& W, int Da, int Db, const EnvView& L,
+                 const EnvView& R, const double* x, double* y) {
+    const int d = W.d;
+    const int64_t n = (int64_t)Da * d * d * Db;
+    const int wl = W.wl, wr = W.wr;
+    ctx->ws_T.ensure(ctx, esz(prec) * 2 * (size_t)n * (wl + wr));
+    void* T = ctx->ws_T.p;
+    const int xs = W.idxI_l >= 0 ? W.idxI_l : 0;
+    load_slot(ctx, prec, x, n, T, xs);
+    std::vector<int> used(wl, 0);
+    for (auto& e : W.ents) used[e.cl] = 1;
+    std::vector<int> chans;
+    for (int c = 0; c < wl; ++c)
+        if (used[c] && c != W.idxI_l) chans.push_back(c);
+    FTD_CHECK(W.idxI_l >= 0 || chans.empty() || true, FTD_EINVAL, "");
+    stage_left(ctx, prec, L, chans, T, xs, Da, Da, d * d, Db, n, TAG_HEFF);
+    std::vector<int> in_slot(wl);
+    for (int c = 0; c < wl; ++c) in_slot[c] = c;
+    // columns: F goes straight into y
+    bool have_direct = false;
+    for (auto& e : W.ents)
+        if (e.cr == W.idxF_r) have_direct = true;
+    MixPlan plan = stage_mix(ctx, prec, W, true, in_slot, wr, wl, {}, T, Da, d, Db, n,
+                             W.idxF_r, y, true, false);
+    // stage 3: y += sum_{cr != F} U[cr] R[cr]^T
+    GemmParams p{};
+    p.M = Da * d * d;
+    p.N = Db;
+    p.K = Db;
+    p.sAm = Db; p.sAk = 1; p.planeA = n; p.a_kcontig = 1;
+    p.sBk = 1; p.sBn = Db; p.planeB = (int64_t)Db * Db; p.b_kcontig = 1;
+    p.sCm = Db; p.sCn = 1; p.planeC = n;
+    p.nprob = 1;
+    p.prob[0].offC = 0;
+    p.prob[0].t0 = 0;
+    int nt = 0;
+    for (int c = 0; c < wr; ++c) {
+        if (c == W.idxF_r || plan.out_slot[c] < 0) continue;
+        FTD_CHECK(nt < kMaxTerms, FTD_EINVAL, "too many channels");
+        p.term[nt].offA = (int64_t)plan.out_slot[c] * 2 * n;
+        p.term[nt].offB = (int64_t)c * 2 * Db * Db;
+        ++nt;
+    }
+    p.prob[0].t1 = nt;
+    p.accumulate = have_direct ? 1 : 0;
+    if (nt > 0)
+        gemm(ctx, prec, true, T, R.p, y, p, TAG_HEFF);
+    else if (!have_direct)
+        k_zero(ctx, y, sizeof(double) * 2 * n);
+    ctx->stats.matvecs++;
+}
+
+// y = K_eff C at the bond between two sites.  L, R: channels of that bond,
+// D x D blocks with L[I] and R[F] materialised as identities.
+static void keff(Ctx* ctx, Prec prec, int w, int idxI, int D, const EnvView& L, const EnvView& R,
+                 const double* x, double* y) {
+    const int64_t n = (int64_t)D * D;
+    ctx->ws_T.ensure(ctx, esz(prec) * 2 * (size_t)n * w);
+    void* T = ctx->ws_T.p;
+    const int xs = idxI >= 0 ? idxI : 0;
+    load_slot(ctx, prec, x, n, T, xs);
+    std::vector<int> chans;
+    for (int c = 0; c < w; ++c)
+        if (c != idxI) chans.push_back(c);
+    stage_left(ctx, prec, L, chans, T, xs, D, D, 1, D, n, TAG_KEFF);
+    GemmParams p{};
+    p.M = D;
+    p.N = D;
+    p.K = D;
+    p.sAm = D; p.sAk = 1; p.planeA = n; p.a_kcontig = 1;
+    p.sBk = 1; p.sBn = D; p.planeB = n; p.b_kcontig = 1;
+    p.sCm = D; p.sCn = 1; p.planeC = n;
+    p.nprob = 1;
+    p.prob[0].offC = 0;
+    p.prob[0].t0 = 0;
+    p.prob[0].t1 = w;
+    for (int c = 0; c < w; ++c) {
+        p.term[c].offA = (int64_t)c * 2 * n;
+        p.term[c].offB = (int64_t)c * 2 * n;
+    }
+    gemm(ctx, prec, true, T, R.p, y, p, TAG_KEFF);
+    ctx->stats.matvecs++;
+}
+
+// Left environment of site i+1 from that of site i and the left-orthonormal
+// A_i (bra = ket).  Output channels W.wr, Db x Db; channel I set to 1.
+static void env_left_update(Ctx* ctx, Prec prec, const MpoSite& W, int Da, int Db,
+                            const EnvView& L, const double* A, const EnvView& Lout) {
+    const int d = W.d;
+    const int64_t n = (int64_t)Da * d * d * Db;
+    const int wl = W.wl, wr = W.wr;
+    ctx->ws_T.ensure(ctx, esz(prec) * 2 * (size_t)n * (wl + wr));
+    void* T = ctx->ws_T.p;
+    const int xs = W.idxI_l >= 0 ? W.idxI_l : 0;
+    load_slot(ctx, prec, A, n, T, xs);
+    std::vector<int> used(wl, 0);
+    for (auto& e : W.ents)
+        if (e.cr != W.idxI_r) used[e.cl] = 1;
+    std::vector<int> chans;
+    for (int c = 0; c < wl; ++c)
+        if (used[c] && c != W.idxI_l) chans.push_back(c);
+    stage_left(ctx, prec, L, chans, T, xs, Da, Da, d * d, Db, n, TAG_NONE);
+    std::vector<int> in_slot(wl);
+    for (int c = 0; c < wl; ++c) in_slot[c] = c;
+    std::vector<int> skip;
+    if (W.idxI_r >= 0) skip.push_back(W.idxI_r);
+    MixPlan plan = stage_mix(ctx, prec, W, true, in_slot, wr, wl, skip, T, Da, d, Db, n, -1,
+                             nullptr, false, false);
+    // Lout[cr] = A^H U[cr]
+    const bool f32 = prec != Prec::F64;
+    const int64_t bb = (int64_t)Db * Db;
+    std::vector<int> outs;
+    for (int c = 0; c < wr; ++c)
+        if (c != W.idxI_r) outs.push_back(c);
+    for (size_t o0 = 0; o0 < outs.size(); o0 += kMaxProbs) {
+        GemmParams p{};
+        p.M = Db;
+        p.N = Db;
+        p.K = Da * d * d;
+        p.sAm = 1; p.sAk = Db; p.planeA = n; p.conjA = 1; p.a_kcontig = 0;
+        p.sBk = Db; p.sBn = 1; p.planeB = n; p.b_kcontig = 0;
+        p.sCm = Db; p.sCn = 1; p.planeC = bb;
+        const size_t o1 = std::min(outs.size(), o0 + kMaxProbs);
+        int np = 0;
+        std::vector<int> zero_out;
+        for (size_t k = o0; k < o1; ++k) {
+            const int c = outs[k];
+            if (plan.out_slot[c] < 0) {
+                zero_out.push_back(c);
+                continue;
+            }
+            p.prob[np].offC = (int64_t)c * 2 * bb;
+            p.prob[np].t0 = np;
+            p.prob[np].t1 = np + 1;
+            p.term[np].offA = (int64_t)xs * 2 * n;
+            p.term[np].offB = (int64_t)plan.out_slot[c] * 2 * n;
+            ++np;
+        }
+        p.nprob = np;
+        if (np) gemm(ctx, prec, !f32, T, T, Lout.p, p, TAG_NONE);
+        for (int c : zero_out)
+            k_zero(ctx, static_cast<char*>(Lout.p) + (size_t)c * 2 * bb * esz(prec), esz(prec) * 2 * bb);
+    }
+    if (W.idxI_r >= 0)
+        eye(ctx, static_cast<char*>(Lout.p) + (size_t)W.idxI_r * 2 * bb * esz(prec), Db, bb, f32);
+}
+
+// Right environment of site i (contraction of sites i..) from that of site
+// i+1 and the right-orthonormal A_i.  Output channels W.wl, Da x Da; F = 1.
+static void env_right_update(Ctx* ctx, Prec prec, const MpoSite& W, int Da, int Db,
+                             const EnvView& R, const double* A, const EnvView& Rout) {
+    const int d = W.d;
+    const int64_t n = (int64_t)Da * d * d * Db;
+    const int wl = W.wl, wr = W.wr;
+    ctx->ws_T.ensure(ctx, esz(prec) * 2 * (size_t)n * (wl + wr));
+    void* T = ctx->ws_T.p;
+    const int as = W.idxF_r >= 0 ? W.idxF_r : 0;
+    load_slot(ctx, prec, A, n, T, as);
+    // T'[cr] = A R[cr]^T, cr != F
+    std::vector<int> used(wr, 0);
+    for (auto& e : W.ents)
+        if (e.cl != W.idxF_l) used[e.cr] = 1;
+    std::vector<int> chans;
+    for (int c = 0; c < wr; ++c)
+        if (used[c] && c != W.idxF_r) chans.push_back(c);
+    for (size_t c0 = 0; c0 < chans.size(); c0 += kMaxProbs) {
+        GemmParams p{};
+        p.M = Da * d * d;
+        p.N = Db;
+        p.K = Db;
+        p.sAm = Db; p.sAk = 1; p.planeA = n; p.a_kcontig = 1;
+        p.sBk = 1; p.sBn = Db; p.planeB = (int64_t)Db * Db; p.b_kcontig = 1;
+        p.sCm = Db; p.sCn = 1; p.planeC = n;
+        const size_t c1 = std::min(chans.size(), c0 + kMaxProbs);
+        p.nprob = (int)(c1 - c0);
+        for (size_t k = c0; k < c1; ++k) {
+            const int c = chans[k];
+            const int j = (int)(k - c0);
+            p.prob[j].offC = (int64_t)c * 2 * n;
+            p.prob[j].t0 = j;
+            p.prob[j].t1 = j + 1;
+            p.term[j].offA = (int64_t)as * 2 * n;
+            p.term[j].offB = (int64_t)c * 2 * Db * Db;
+        }
+        gemm(ctx, prec, prec == Prec::F64, T, R.p, T, p, TAG_NONE);
+    }
+    std::vector<int> in_slot(wr);
+    for (int c = 0; c < wr; ++c) in_slot[c] = c;
+    std::vector<int> skip;
+    if (W.idxF_l >= 0) skip.push_back(W.idxF_l);
+    MixPlan plan = stage_mix(ctx, prec, W, false, in_slot, wl, wr, skip, T, Da, d, Db, n, -1,
+                             nullptr, false, false);
+    const bool f32 = prec != Prec::F64;
+    const int64_t aa = (int64_t)Da * Da;
+    const int64_t K = (int64_t)d * d * Db;
+    std::vector<int> outs;
+    for (int c = 0; c < wl; ++c)
+        if (c != W.idxF_l) outs.push_back(c);
+    for (size_t o0 = 0; o0 < outs.size(); o0 += kMaxProbs) {
+        GemmParams p{};
+        p.M = Da;
+        p.N = Da;
+        p.K = (int)K;
+        p.sAm = K; p.sAk = 1; p.planeA = n; p.conjA = 1; p.a_kcontig = 1;
+        p.sBk = 1; p.sBn = K; p.planeB = n; p.b_kcontig = 1;
+        p.sCm = Da; p.sCn = 1; p.planeC = aa;
+        const size_t o1 = std::min(outs.size(), o0 + kMaxProbs);
+        int np = 0;
+        std::vector<int> zero_out;
+        for (size_t k = o0; k < o1; ++k) {
+            const int c = outs[k];
+            if (plan.out_slot[c] < 0) {
+                zero_out.push_back(c);
+                continue;
+            }
+            p.prob[np].offC = (int64_t)c * 2 * aa;
+            p.prob[np].t0 = np;
+            p.prob[np].t1 = np + 1;
+            p.term[np].offA = (int64_t)as * 2 * n;
+            p.term[np].offB = (int64_t)plan.out_slot[c] * 2 * n;
+            ++np;
+        }
+        p.nprob = np;
+        if (np) gemm(ctx, prec, !f32, T, T, Rout.p, p, TAG_NONE);
+        for (int c : zero_out)
+            k_zero(ctx, static_cast<char*>(Rout.p) + (size_t)c * 2 * aa * esz(prec), esz(prec) * 2 * aa);
+    }
+    if (W.idxF_l >= 0)
+        eye(ctx, static_cast<char*>(Rout.p) + (size_t)W.idxF_l * 2 * aa * esz(prec), Da, aa, f32);
+}
+
+// ================================================================ Krylov
+// x <- exp(z Op) x by Lanczos with full (twice-applied classical
+// Gram-Schmidt) reorthogonalisation in float64.
+static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*)>& op, double* x,
+                       int64_t n, cplx z, double tol, int mmax) {
+    FTD_CHECK(mmax >= 1 && mmax < kMaxKrylov, FTD_EINVAL, "Krylov mmax out of range");
+    const int64_t vs = 2 * n;
+    ctx->ws_Krylov.ensure(ctx, sizeof(double) * (size_t)vs * (mmax + 1));
+    double* V = ctx->ws_Krylov.as<double>();
+    KrylovDev kd = ctx->kd;
+    k_nrm2(ctx, x, n, n, kd.nrm + 1);
+    k_copy_f64(ctx, x, V, vs);
+    k_scale_by_dev(ctx, V, n, n, kd.nrm + 1, 0);
+    const int kmax = (int)std::min<int64_t>(mmax, n);
+    for (int k = 0; k < kmax; ++k) {
+        double* vk = V + (int64_t)k * vs;
+        double* w = V + (int64_t)(k + 1) * vs;
+        op(vk, w);
+        k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
+        k_set_alpha(ctx, kd, k);
+        k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
+        k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
+        k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
+        k_nrm2(ctx, w, n, n, kd.nrm);
+        const int exhausted = (k + 1 == n) ? 1 : 0;
+        k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted);
+        k_lanczos_post(ctx, kd, k + 1, w, n, n);
+        FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i, kd.flag, 3 * sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+        const int conv = ctx->h_pinned_i[0], failed = ctx->h_pinned_i[2];
+        FTD_CHECK(!failed || conv, FTD_ENOCONV, "Krylov exponential: non-finite values");
+        if (conv) {
+            k_lincomb(ctx, V, vs, k + 1, kd.u, kd.nrm + 1, x, n, n);
+            ctx->stats.krylov_vectors += k + 1;
+            ctx->stats.expm_calls += 1;
+            ctx->stats.krylov_max = std::max<int64_t>(ctx->stats.krylov_max, k + 1);
+            return k + 1;
+        }
+    }
+    throw Error{FTD_ENOCONV, "Krylov exponential did not converge within mmax vectors"};
+}
+
+// ============================================================= gauge moves
+static void ensure_env_arrays(Ctx* ctx, int L) {
+    if ((int)ctx->envL.size() < L + 1) {
+        ctx->envL.resize(L + 1);
+        ctx->envL_w.resize(L + 1);
+        ctx->envL_D.resize(L + 1);
+    }
+    if ((int)ctx->envR.size() < L + 1) {
+        ctx->envR.resize(L + 1);
+        ctx->envR_w.resize(L + 1);
+        ctx->envR_D.resize(L + 1);
+    }
+}
+static EnvView envL_view(Ctx* ctx, int i, Prec prec) {
+    return {ctx->envL[i].p, ctx->envL_w[i], ctx->envL_D[i], ctx->envL_D[i]};
+}
+static EnvView envR_view(Ctx* ctx, int i, Prec prec) {
+    return {ctx->envR[i].p, ctx->envR_w[i], ctx->envR_D[i], ctx->envR_D[i]};
+}
+
+static void build_right_envs(Ctx* ctx, const Mpo* H, const Mps* psi, int from) {
+    const int L = psi->L;
+    const Prec prec = psi->prec;
+    ensure_env_arrays(ctx, L);
+    EnvView b = env_get(ctx, ctx->envR, ctx->envR_w, ctx->envR_D, L, 1, 1, prec);
+    boundary_env(ctx, b, prec);
+    for (int i = L - 1; i >= from; --i) {
+        const MpoSite& W = H->s[i];
+        EnvView R = envR_view(ctx, i + 1, prec);
+        EnvView out = env_get(ctx, ctx->envR, ctx->envR_w, ctx->envR_D, i, W.wl, psi->Dl[i], prec);
+        env_right_update(ctx, prec, W, psi->Dl[i], psi->Dr[i], R, psi->A[i], out);
+    }
+}
+static void build_left_envs(Ctx* ctx, const Mpo* H, const Mps* psi, int upto) {
+    const int L = psi->L;
+    const Prec prec = psi->prec;
+    ensure_env_arrays(ctx, L);
+    EnvView b = env_get(ctx, ctx->envL, ctx->envL_w, ctx->envL_D, 0, 1, 1, prec);
+    boundary_env(ctx, b, prec);
+    for (int i = 0; i < upto; ++i) {
+        const MpoSite& W = H->s[i];
+        EnvView Lv = envL_view(ctx, i, prec);
+        EnvView out = env_get(ctx, ctx->envL, ctx->envL_w, ctx->envL_D, i + 1, W.wr, psi->Dr[i], prec);
+        env_left_update(ctx, prec, W, psi->Dl[i], psi->Dr[i], Lv, psi->A[i], out);
+    }
+}
+
+// new A_{i+1} = C A_{i+1}  (C: Dr x Dr)
+static void absorb_right(Ctx* ctx, Mps* psi, int i, const double* C) {
+    const int D = psi->Dr[i];
+    const int64_t nn = psi->size(i + 1);
+    const int64_t cols = nn / D;
+    ctx->ws_site.ensure(ctx, sizeof(double) * 2 * nn);
+    double* tmp = ctx->ws_site.as<double>();
+    GemmParams p{};
+    p.M = D; p.N = (int)cols; p.K = D;
+    p.sAm = D; p.sAk = 1; p.planeA = (int64_t)D * D; p.a_kcontig = 1;
+    p.sBk = cols; p.sBn = 1; p.planeB = nn; p.b_kcontig = 0;
+    p.sCm = cols; p.sCn = 1; p.planeC = nn;
+    p.nprob = 1; p.prob[0].t1 = 1;
+    gemm(ctx, Prec::F64, true, C, psi->A[i + 1], tmp, p, TAG_NONE);
+    k_copy_f64(ctx, tmp, psi->A[i + 1], 2 * nn);
+}
+// new A_{i-1} = A_{i-1} C  (C: Dl_i x Dl_i)
+static void absorb_left(Ctx* ctx, Mps* psi, int i, const double* C) {
+    const int D = psi->Dl[i];
+    const int64_t nn = psi->size(i - 1);
+    const int64_t rows = nn / D;
+    ctx->ws_site.ensure(ctx, sizeof(double) * 2 * nn);
+    double* tmp = ctx->ws_site.as<double>();
+    GemmParams p{};
+    p.M = (int)rows; p.N = D; p.K = D;
+    p.sAm = D; p.sAk = 1; p.planeA = nn; p.a_kcontig = 1;
+    p.sBk = D; p.sBn = 1; p.planeB = (int64_t)D * D; p.b_kcontig = 0;
+    p.sCm = D; p.sCn = 1; p.planeC = nn;
+    p.nprob = 1; p.prob[0].t1 = 1;
+    gemm(ctx, Prec::F64, true, psi->A[i - 1], C, tmp, p, TAG_NONE);
+    k_copy_f64(ctx, tmp, psi->A[i - 1], 2 * nn);
+}
+
+// ============================================================ TDVP sweep
+void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
+    const int L = psi->L;
+    FTD_CHECK(H->L == L, FTD_EINVAL, "MPO and MPS lengths differ");
+    const Prec prec = psi->prec;
+    build_right_envs(ctx, H, psi, 1);
+    EnvView b = env_get(ctx, ctx->envL, ctx->envL_w, ctx->envL_D, 0, 1, 1, prec);
+    boundary_env(ctx, b, prec);
+    const cplx h = 0.5 * z;
+    ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * 1024 * 1024);
+    auto site_evolve = [&](int i) {
+        const MpoSite& W = H->s[i];
+        EnvView Lv = envL_view(ctx, i, prec), Rv = envR_view(ctx, i + 1, prec);
+        const int Da = psi->Dl[i], Db = psi->Dr[i];
+        auto op = [&](const double* x, double* y) { heff(ctx, prec, W, Da, Db, Lv, Rv, x, y); };
+        expm_krylov(ctx, op, psi->A[i], psi->size(i), h, tol, mmax);
+    };
+    auto bond_evolve = [&](int i, double* C, int D) {
+        // bond between sites i and i+1: envL[i+1], envR[i+1]
+        const MpoSite& W = H->s[i];
+        EnvView Lv = envL_view(ctx, i + 1, prec), Rv = envR_view(ctx, i + 1, prec);
+        auto op = [&](const double* x, double* y) { keff(ctx, prec, W.wr, W.idxI_r, D, Lv, Rv, x, y); };
+        expm_krylov(ctx, op, C, (int64_t)D * D, -h, tol, mmax);
+    };
+    for (int i = 0; i < L - 1; ++i) {
+        site_evolve(i);
+        const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
+        ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Db * Db);
+        double* C = ctx->ws_tmp1.as<double>();
+        qr_chol(ctx, psi->A[i], (int64_t)Da * d * d, Db, C);
+        EnvView Lv = envL_view(ctx, i, prec);
+        EnvView out = env_get(ctx, ctx->envL, ctx->envL_w, ctx->envL_D, i + 1, H->s[i].wr, Db, prec);
+        env_left_update(ctx, prec, H->s[i], Da, Db, Lv, psi->A[i], out);
+        bond_evolve(i, C, Db);
+        absorb_right(ctx, psi, i, C);
+    }
+    site_evolve(L - 1);
+    site_evolve(L - 1);
+    for (int i = L - 1; i >= 1; --i) {
+        const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
+        ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Da * Da);
+        double* C = ctx->ws_tmp1.as<double>();
+        lq_chol(ctx, psi->A[i], Da, (int64_t)d * d * Db, C);
+        EnvView Rv = envR_view(ctx, i + 1, prec);
+        EnvView out = env_get(ctx, ctx->envR, ctx->envR_w, ctx->envR_D, i, H->s[i].wl, Da, prec);
+        env_right_update(ctx, prec, H->s[i], Da, Db, Rv, psi->A[i], out);
+        bond_evolve(i - 1, C, Da);
+        absorb_left(ctx, psi, i, C);
+        site_evolve(i - 1);
+    }
+}
+
+// ============================================================ MPS algebra
+Mps* mpo_apply(Ctx* ctx, const Mpo* O, const Mps* psi) {
+    const int L = psi->L;
+    std::vector<int> Dl(L), Dr(L);
+    for (int i = 0; i < L; ++i) {
+        Dl[i] = psi->Dl[i] * O->s[i].wl;
+        Dr[i] = psi->Dr[i] * O->s[i].wr;
+    }
+    Mps* out = mps_alloc(ctx, Dl, psi->d, Dr, psi->prec);
+    for (int i = 0; i < L; ++i) {
+        const MpoSite& W = O->s[i];
+        k_mpo_apply(ctx, psi->A[i], psi->Dl[i], W.d, psi->Dr[i], W.ops64, 2 * (int64_t)W.d * W.d,
+                    W.wl, W.wr, W.apply_ents, (int)W.ents.size(), out->A[i]);
+    }
+    out->log_norm = psi->log_norm;
+    return out;
+}
+
+Mps* mps_add(Ctx* ctx, const Mps* a, const Mps* b, cplx c) {
+    const int L = a->L;
+    FTD_CHECK(b->L == L, FTD_EINVAL, "mps_add: lengths differ");
+    std::vector<int> Dl(L), Dr(L);
+    for (int i = 0; i < L; ++i) {
+        Dl[i] = (i == 0) ? 1 : a->Dl[i] + b->Dl[i];
+        Dr[i] = (i == L - 1) ? 1 : a->Dr[i] + b->Dr[i];
+    }
+    Mps* out = mps_alloc(ctx, Dl, a->d, Dr, a->prec);
+    for (int i = 0; i < L; ++i) {
+        const int dd = a->d[i] * a->d[i];
+        k_zero(ctx, out->A[i], sizeof(double) * 2 * out->size(i));
+        k_embed(ctx, a->A[i], a->Dl[i], dd, a->Dr[i], out->A[i], Dl[i], Dr[i], 0, 0, 1.0, 0.0);
+        const int a0 = (i == 0) ? 0 : a->Dl[i];
+        const int b0 = (i == L - 1) ? 0 : a->Dr[i];
+        const cplx s = (i == 0) ? c : cplx(1.0, 0.0);
+        k_embed(ctx, b->A[i], b->Dl[i], dd, b->Dr[i], out->A[i], Dl[i], Dr[i], a0, b0, s.real(), s.imag());
+    }
+    out->log_norm = a->log_norm;
+    return out;
+}
+
+static int truncation_rank(const std::vector<double>& s, int D, double cutoff) {
+    if (s.empty() || s[0] == 0.0) return 1;
+    int k = 0;
+    for (double x : s)
+        if (x > cutoff * s[0]) ++k;
+    k = std::max(1, std::min(k, D));
+    while (k > 1 && k < (int)s.size() && (s[k - 1] - s[k]) <= 1e-8 * s[k - 1]) --k;
+    return k;
+}
+
+// Left QR sweep (Householder) then right-to-left SVD truncation (Jacobi).
+Mps* compress(Ctx* ctx, Mps* X, int D, double cutoff, bool consume) {
+    Mps* Y = consume ? X : mps_clone(X);
+    const int L = Y->L;
+    for (int i = 0; i < L - 1; ++i) {
+        const int d = Y->d[i];
+        const int64_t m = (int64_t)Y->Dl[i] * d * d, nc = Y->Dr[i];
+        const int r = (int)std::min<int64_t>(m, nc);
+        double* Q = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * r));
+        ctx->ws_tmp2.ensure(ctx, sizeof(double) * 2 * (size_t)r * nc);
+        double* R = ctx->ws_tmp2.as<double>();
+        qr_householder(ctx, Y->A[i], m, nc, Q, R);
+        set_site(ctx, Y, i, Y->Dl[i], r, Q);
+        // A_{i+1} <- R A_{i+1}
+        const int64_t nn = Y->size(i + 1);
+        const int64_t cols = nn / nc;
+        double* B = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * r * cols));
+        GemmParams p{};
+        p.M = r; p.N = (int)cols; p.K = (int)nc;
+        p.sAm = nc; p.sAk = 1; p.planeA = (int64_t)r * nc; p.a_kcontig = 1;
+        p.sBk = cols; p.sBn = 1; p.planeB = nn; p.b_kcontig = 0;
+        p.sCm = cols; p.sCn = 1; p.planeC = (int64_t)r * cols;
+        p.nprob = 1; p.prob[0].t1 = 1;
+        gemm(ctx, Prec::F64, true, R, Y->A[i + 1], B, p, TAG_NONE);
+        set_site(ctx, Y, i + 1, r, Y->Dr[i + 1], B);
+    }
+    for (int i = L - 1; i >= 1; --i) {
+        const int d = Y->d[i];
+        const int64_t rows = Y->Dl[i], c = (int64_t)d * d * Y->Dr[i];
+        const int64_t ns = std::min(rows, c);
+        // left vectors times S (rows x k, col-major) and new A_i (k x c, row-major)
+        ctx->ws_svd1.ensure(ctx, sizeof(double) * 2 * (size_t)(rows * c + ns * ns + rows * ns + ns));
+        double* Ub = ctx->ws_svd1.as<double>();
+        double* Vb = Ub + 2 * rows * c;
+        double* Sd = Vb + 2 * ns * ns;
+        std::vector<double> S(ns);
+        std::vector<int> perm(ns);
+        int k = 0;
+        double* LS = nullptr;
+        double* Anew = nullptr;
+        auto finish_perm = [&]() {
+            FTD_HIP(hipMemcpyAsync(S.data(), Sd, sizeof(double) * ns, hipMemcpyDeviceToHost, ctx->stream));
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+            std::iota(perm.begin(), perm.end(), 0);
+            std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return S[a] > S[b]; });
+            std::vector<double> ss(ns);
+            for (int j = 0; j < ns; ++j) ss[j] = S[perm[j]];
+            k = truncation_rank(ss, D, cutoff);
+        };
+        ctx->ws_perm.ensure(ctx, sizeof(int) * ns + sizeof(double) * 2 * ns + 64);
+        int* dperm = ctx->ws_perm.as<int>();
+        double* dsc = reinterpret_cast<double*>(static_cast<char*>(ctx->ws_perm.p) + ((sizeof(int) * ns + 15) / 16) * 16);
+        auto upload = [&](const std::vector<double>& sc) {
+            std::vector<int> pk(perm.begin(), perm.begin() + k);
+            FTD_HIP(hipMemcpyAsync(dperm, pk.data(), sizeof(int) * k, hipMemcpyHostToDevice, ctx->stream));
+            FTD_HIP(hipMemcpyAsync(dsc, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+        };
+        if (c <= rows) {
+            // C = U S V^H directly: U (rows x c, scaled), V (c x c)
+            svd_jacobi(ctx, Y->A[i], rows, c, Ub, Sd, Vb);
+            finish_perm();
+            upload(std::vector<double>(k, 1.0));
+            LS = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * k));
+            gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(Ub, rows, rows * c, dperm, nullptr, k, 0, LS, rows * k);
+            Anew = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * c * k));
+            gather_cols_kernel<<<gr(c * k), 256, 0, ctx->stream>>>(Vb, c, c * c, dperm, nullptr, k, 1, Anew, c * k);
+        } else {
+            // work on C^H (c x rows)
+            ctx->ws_tmp3.ensure(ctx, sizeof(double) * 2 * (size_t)c * rows);
+            double* CH = ctx->ws_tmp3.as<double>();
+            k_transpose(ctx, Y->A[i], rows, c, rows * c, CH, rows * c, 1);
+            if (c >= 2 * rows && rows > 1) {
+                double* Q = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * c * rows));
+                double* R = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * rows));
+                qr_householder(ctx, CH, c, rows, Q, R);
+                // R = U' S V'^H
+                svd_jacobi(ctx, R, rows, rows, Ub, Sd, Vb);
+                finish_perm();
+                std::vector<double> sc(k), inv(k);
+                for (int j = 0; j < k; ++j) {
+                    sc[j] = S[perm[j]];
+                    inv[j] = S[perm[j]] > 0.0 ? 1.0 / S[perm[j]] : 0.0;
+                }
+                upload(sc);
+                LS = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * k));
+                gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(Vb, rows, rows * rows, dperm, dsc, k, 0, LS, rows * k);
+                upload(inv);
+                double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * k));
+                gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(Ub, rows, rows * rows, dperm, dsc, k, 0, G, rows * k);
+                // A_new (k x c) = conj(Q G)^T
+                Anew = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * c * k));
+                GemmParams p{};
+                p.M = (int)c; p.N = k; p.K = (int)rows;
+                p.sAm = rows; p.sAk = 1; p.planeA = c * rows; p.conjA = 1; p.a_kcontig = 1;
+                p.sBk = 1; p.sBn = rows; p.planeB = rows * k; p.conjB = 1; p.b_kcontig = 1;
+                p.sCm = 1; p.sCn = c; p.planeC = c * k;
+                p.nprob = 1; p.prob[0].t1 = 1;
+                gemm(ctx, Prec::F64, true, Q, G, Anew, p, TAG_NONE);
+                FTD_HIP(hipStreamSynchronize(ctx->stream));
+                dev_free(ctx, Q);
+                dev_free(ctx, R);
+                dev_free(ctx, G);
+            } else {
+                svd_jacobi(ctx, CH, c, rows, Ub, Sd, Vb);
+                finish_perm();
+                std::vector<double> sc(k), inv(k);
+                for (int j = 0; j < k; ++j) {
+                    sc[j] = S[perm[j]];
+                    inv[j] = S[perm[j]] > 0.0 ? 1.0 / S[perm[j]] : 0.0;
+                }
+                upload(sc);
+                LS = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * k));
+                gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(Vb, rows, rows * rows, dperm, dsc, k, 0, LS, rows * k);
+                upload(inv);
+                Anew = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * c * k));
+                gather_cols_kernel<<<gr(c * k), 256, 0, ctx->stream>>>(Ub, c, c * rows, dperm, dsc, k, 1, Anew, c * k);
+            }
+        }
+        FTD_HIP(hipGetLastError());
+        set_site(ctx, Y, i, k, Y->Dr[i], Anew);
+        // A_{i-1} <- A_{i-1} LS
+        const int64_t nn = Y->size(i - 1);
+        const int64_t r2 = nn / rows;
+        double* B = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * r2 * k));
+        GemmParams p{};
+        p.M = (int)r2; p.N = k; p.K = (int)rows;
+        p.sAm = rows; p.sAk = 1; p.planeA = nn; p.a_kcontig = 1;
+        p.sBk = 1; p.sBn = rows; p.planeB = rows * k; p.b_kcontig = 1;
+        p.sCm = k; p.sCn = 1; p.planeC = r2 * k;
+        p.nprob = 1; p.prob[0].t1 = 1;
+        gemm(ctx, Prec::F64, true, Y->A[i - 1], LS, B, p, TAG_NONE);
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+        dev_free(ctx, LS);
+        set_site(ctx, Y, i - 1, Y->Dl[i - 1], k, B);
+    }
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
+    return Y;
+}
+
+Mps* apply_compress(Ctx* ctx, const Mpo* O, const Mps* psi, int D, double cutoff) {
+    Mps* X = mpo_apply(ctx, O, psi);
+    try {
+        return compress(ctx, X, D, cutoff, true);
+    } catch (...) {
+        mps_free(X);
+        throw;
+    }
+}
+
+// ============================================================== overlap
+// <bra| O |ket> by a left-to-right transfer contraction in float64.
+cplx overlap(Ctx* ctx, const Mps* bra, const Mpo* O, const Mps* ket) {
+    const int L = bra->L;
+    FTD_CHECK(ket->L == L && O->L == L, FTD_EINVAL, "overlap: lengths differ");
+    DBuf Ea, Eb;
+    std::vector<double> one = {1.0, 0.0};
+    Ea.ensure(ctx, sizeof(double) * 2);
+    FTD_HIP(hipMemcpyAsync(Ea.p, one.data(), sizeof(double) * 2, hipMemcpyHostToDevice, ctx->stream));
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
+    int w = 1;
+    for (int i = 0; i < L; ++i) {
+        const MpoSite& W = O->s[i];
+        const int d = W.d;
+        const int Da1 = bra->Dl[i], Db1 = bra->Dr[i];
+        const int Da2 = ket->Dl[i], Db2 = ket->Dr[i];
+        FTD_CHECK(w == W.wl, FTD_EINVAL, "overlap: channel mismatch");
+        const int64_t n = (int64_t)Da1 * d * d * Db2;   // T shape (a', p, q, b)
+        const int64_t nk = ket->size(i);
+        const int wl = W.wl, wr = W.wr;
+        ctx->ws_T.ensure(ctx, sizeof(double) * 2 * (size_t)n * (wl + wr + 1) + sizeof(double) * 2 * nk);
+        double* T = ctx->ws_T.as<double>();
+        // ket tensor into the extra slot wl + wr
+        const int ks = wl + wr;
+        // stage_left expects X laid out with slot stride 2n; use a direct GEMM here
+        k_copy_f64(ctx, ket->A[i], T + (int64_t)ks * 2 * n, 2 * nk);
+        {
+            GemmParams p{};
+            p.M = Da1; p.N = d * d * Db2; p.K = Da2;
+            p.sAm = Da2; p.sAk = 1; p.planeA = (int64_t)Da1 * Da2; p.a_kcontig = 1;
+            p.sBk = (int64_t)d * d * Db2; p.sBn = 1; p.planeB = nk; p.b_kcontig = 0;
+            p.sCm = (int64_t)d * d * Db2; p.sCn = 1; p.planeC = n;
+            p.nprob = wl;
+            for (int c = 0; c < wl; ++c) {
+                p.prob[c].offC = (int64_t)c * 2 * n;
+                p.prob[c].t0 = c;
+                p.prob[c].t1 = c + 1;
+                p.term[c].offA = (int64_t)c * 2 * Da1 * Da2;
+                p.term[c].offB = (int64_t)ks * 2 * n;
+            }
+            gemm(ctx, Prec::F64, true, Ea.p, T, T, p, TAG_NONE);
+        }
+        std::vector<int> in_slot(wl);
+        for (int c = 0; c < wl; ++c) in_slot[c] = c;
+        MixPlan plan = stage_mix(ctx, Prec::F64, W, true, in_slot, wr, wl, {}, T, Da1, d, Db2, n,
+                                 -1, nullptr, true, false);
+        const int64_t bb = (int64_t)Db1 * Db2;
+        Eb.ensure(ctx, sizeof(double) * 2 * (size_t)wr * bb);
+        for (int c = 0; c < wr; ++c)
+            if (plan.out_slot[c] < 0) k_zero(ctx, Eb.as<double>() + (int64_t)c * 2 * bb, sizeof(double) * 2 * bb);
+        GemmParams p{};
+        p.M = Db1; p.N = Db2; p.K = Da1 * d * d;
+        p.sAm = 1; p.sAk = Db1; p.planeA = bra->size(i); p.conjA = 1; p.a_kcontig = 0;
+        p.sBk = Db2; p.sBn = 1; p.planeB = n; p.b_kcontig = 0;
+        p.sCm = Db2; p.sCn = 1; p.planeC = bb;
+        int np = 0;
+        for (int c = 0; c < wr; ++c) {
+            if (plan.out_slot[c] < 0) continue;
+            p.prob[np].offC = (int64_t)c * 2 * bb;
+            p.prob[np].t0 = np;
+            p.prob[np].t1 = np + 1;
+            p.term[np].offA = 0;
+            p.term[np].offB = (int64_t)plan.out_slot[c] * 2 * n;
+            ++np;
+        }
+        p.nprob = np;
+        // bra operand and T are different buffers: run per problem with A = bra
+        if (np) gemm(ctx, Prec::F64, true, bra->A[i], T, Eb.p, p, TAG_NONE);
+        std::swap(Ea, Eb);
+        w = wr;
+    }
+    std::vector<double> out(2);
+    FTD_HIP(hipMemcpyAsync(out.data(), Ea.p, sizeof(double) * 2, hipMemcpyDeviceToHost, ctx->stream));
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
+    Ea.release(ctx);
+    Eb.release(ctx);
+    return cplx(out[0], out[1]);
+}
+
+// ========================================================= kernel access
+void heff_apply_host(Ctx* ctx, const Mpo* H, const Mps* psi, int site, const double* x,
+                     double* y, int nrep) {
+    const int L = psi->L;
+    FTD_CHECK(site >= 0 && site < L, FTD_EINVAL, "site out of range");
+    const Prec prec = psi->prec;
+    build_left_envs(ctx, H, psi, site);
+    build_right_envs(ctx, H, psi, site + 1);
+    const int64_t n = psi->size(site);
+    double* dx = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n));
+    double* dy = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n));
+    std::vector<double> hx(2 * n);
+    for (int64_t k = 0; k < n; ++k) {
+        hx[k] = x[2 * k];
+        hx[k + n] = x[2 * k + 1];
+    }
+    FTD_HIP(hipMemcpyAsync(dx, hx.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, ctx->stream));
+    EnvView Lv = envL_view(ctx, site, prec), Rv = envR_view(ctx, site + 1, prec);
+    for (int r = 0; r < std::max(1, nrep); ++r)
+        heff(ctx, prec, H->s[site], psi->Dl[site], psi->Dr[site], Lv, Rv, dx, dy);
+    FTD_HIP(hipMemcpyAsync(hx.data(), dy, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, ctx->stream));
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < n; ++k) {
+        y[2 * k] = hx[k];
+        y[2 * k + 1] = hx[k + n];
+    }
+    dev_free(ctx, dx);
+    dev_free(ctx, dy);
+}
+
+}  // namespace ftd

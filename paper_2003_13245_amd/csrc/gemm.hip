@@ -1,0 +1,315 @@
+// Complex split-plane GEMM on CDNA4 matrix cores.
+//
+// One workgroup (4 wavefronts) computes a 64x64 tile of C.  Each wavefront
+// owns a 32x32 quadrant as 2x2 blocks of 16x16 MFMA outputs; every k-step of
+// 4 issues four real products per block (re*re, im*im, re*im, im*re) into
+// three accumulators, so Re C = RR - II and Im C = RI + IR.  Operands are
+// staged through LDS as [plane][k][m] / [plane][k][n] so that the 16 lanes
+// sharing a k row read 16 consecutive elements.  Conjugation is applied while
+// staging.  Problems (independent outputs) and summed terms (products added
+// into the same output) are described by offset tables passed by value, which
+// is how the channel sums of the effective Hamiltonian map onto one launch.
+#include "common.h"
+
+namespace ftd {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Output row of accumulator register r in lane `lane` within a 16x16 block.
+// f64 16x16x4 spreads rows as 4*r + lane/16, f32 16x16x4 as 4*(lane/16) + r
+// (checked by a lane-layout probe on gfx950).  Columns are lane % 16 and the
+// operand layouts are A[i][k] in lane i + 16k, B[k][j] in lane j + 16k.
+template <typename T>
+struct AccT;
+template <>
+struct AccT<double> {
+    typedef d4 type;
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct AccT<float> {
+    typedef f4 type;
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int GBM = 64, GBN = 64, GBK = 16, GNT = 256, GPAD = 1;
+
+template <typename Tin, typename Tout, bool AK, bool BKC>
+__global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
+                                                   const Tin* __restrict__ B,
+                                                   Tout* __restrict__ C,
+                                                   Tin* __restrict__ partial, const GemmParams p) {
+    typedef typename AccT<Tin>::type acc_t;
+    __shared__ Tin As[2][GBK][GBM + GPAD];
+    __shared__ Tin Bs[2][GBK][GBN + GPAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int prob = blockIdx.z % p.nprob;
+    const int split = blockIdx.z / p.nprob;
+
+    acc_t RR[2][2], II[2][2], IM[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            RR[i][j] = acc_t{0, 0, 0, 0};
+            II[i][j] = acc_t{0, 0, 0, 0};
+            IM[i][j] = acc_t{0, 0, 0, 0};
+        }
+
+    const int ktiles = (p.K + GBK - 1) / GBK;
+    const int t0 = p.prob[prob].t0, t1 = p.prob[prob].t1;
+    const int total = (t1 - t0) * ktiles;
+    const int per = (total + p.ksplit - 1) / p.ksplit;
+    const int g0 = split * per;
+    const int g1 = min(total, g0 + per);
+    const Tin sa = p.conjA ? Tin(-1) : Tin(1);
+    const Tin sb = p.conjB ? Tin(-1) : Tin(1);
+
+    for (int g = g0; g < g1; ++g) {
+        const int t = t0 + g / ktiles;
+        const int k0 = (g % ktiles) * GBK;
+        const Tin* Ab = A + p.term[t].offA;
+        const Tin* Bb = B + p.term[t].offB;
+        if (AK) {
+            const int kk = tid & 15;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int mm = (tid >> 4) + 16 * i;
+                const int gm = m0 + mm, gk = k0 + kk;
+                Tin re = 0, im = 0;
+                if (gm < p.M && gk < p.K) {
+                    const int64_t idx = (int64_t)gm * p.sAm + (int64_t)gk * p.sAk;
+                    re = Ab[idx];
+                    im = Ab[idx + p.planeA];
+                }
+                As[0][kk][mm] = re;
+                As[1][kk][mm] = sa * im;
+            }
+        } else {
+            const int mm = tid & 63;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kk = (tid >> 6) + 4 * i;
+                const int gm = m0 + mm, gk = k0 + kk;
+                Tin re = 0, im = 0;
+                if (gm < p.M && gk < p.K) {
+                    const int64_t idx = (int64_t)gm * p.sAm + (int64_t)gk * p.sAk;
+                    re = Ab[idx];
+                    im = Ab[idx + p.planeA];
+                }
+                As[0][kk][mm] = re;
+                As[1][kk][mm] = sa * im;
+            }
+        }
+        if (BKC) {
+            const int kk = tid & 15;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int nn = (tid >> 4) + 16 * i;
+                const int gn = n0 + nn, gk = k0 + kk;
+                Tin re = 0, im = 0;
+                if (gn < p.N && gk < p.K) {
+                    const int64_t idx = (int64_t)gk * p.sBk + (int64_t)gn * p.sBn;
+                    re = Bb[idx];
+                    im = Bb[idx + p.planeB];
+                }
+                Bs[0][kk][nn] = re;
+                Bs[1][kk][nn] = sb * im;
+            }
+        } else {
+            const int nn = tid & 63;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kk = (tid >> 6) + 4 * i;
+                const int gn = n0 + nn, gk = k0 + kk;
+                Tin re = 0, im = 0;
+                if (gn < p.N && gk < p.K) {
+                    const int64_t idx = (int64_t)gk * p.sBk + (int64_t)gn * p.sBn;
+                    re = Bb[idx];
+                    im = Bb[idx + p.planeB];
+                }
+                Bs[0][kk][nn] = re;
+                Bs[1][kk][nn] = sb * im;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GBK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            const int c = lane & 15;
+            Tin ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ar[i] = As[0][kr][wm * 32 + i * 16 + c];
+                ai[i] = As[1][kr][wm * 32 + i * 16 + c];
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                br[j] = Bs[0][kr][wn * 32 + j * 16 + c];
+                bi[j] = Bs[1][kr][wn * 32 + j * 16 + c];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    RR[i][j] = mfma4(ar[i], br[j], RR[i][j]);
+                    II[i][j] = mfma4(ai[i], bi[j], II[i][j]);
+                    IM[i][j] = mfma4(ar[i], bi[j], IM[i][j]);
+                    IM[i][j] = mfma4(ai[i], br[j], IM[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+
+    const int64_t MN = (int64_t)p.M * p.N;
+    const int64_t pplane = (int64_t)p.ksplit * p.nprob * MN;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + i * 16 + AccT<Tin>::row(lane, r);
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < p.M && col < p.N) {
+                    const Tin cr = RR[i][j][r] - II[i][j][r];
+                    const Tin ci = IM[i][j][r];
+                    if (p.ksplit > 1) {
+                        const int64_t idx = ((int64_t)split * p.nprob + prob) * MN + (int64_t)row * p.N + col;
+                        partial[idx] = cr;
+                        partial[idx + pplane] = ci;
+                    } else {
+                        const int64_t idx = p.prob[prob].offC + (int64_t)row * p.sCm + (int64_t)col * p.sCn;
+                        if (p.accumulate) {
+                            C[idx] += (Tout)cr;
+                            C[idx + p.planeC] += (Tout)ci;
+                        } else {
+                            C[idx] = (Tout)cr;
+                            C[idx + p.planeC] = (Tout)ci;
+                        }
+                    }
+                }
+            }
+}
+
+template <typename Tin, typename Tout>
+__global__ void gemm_reduce_kernel(const Tin* __restrict__ partial, Tout* __restrict__ C,
+                                   const GemmParams p) {
+    const int64_t MN = (int64_t)p.M * p.N;
+    const int64_t pplane = (int64_t)p.ksplit * p.nprob * MN;
+    const int64_t tot = MN * p.nprob;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int prob = (int)(e / MN);
+        const int64_t rc = e % MN;
+        const int row = (int)(rc / p.N), col = (int)(rc % p.N);
+        Tout sr = 0, si = 0;
+        for (int s = 0; s < p.ksplit; ++s) {
+            const int64_t idx = ((int64_t)s * p.nprob + prob) * MN + rc;
+            sr += (Tout)partial[idx];
+            si += (Tout)partial[idx + pplane];
+        }
+        const int64_t idx = p.prob[prob].offC + (int64_t)row * p.sCm + (int64_t)col * p.sCn;
+        if (p.accumulate) {
+            C[idx] += sr;
+            C[idx + p.planeC] += si;
+        } else {
+            C[idx] = sr;
+            C[idx + p.planeC] = si;
+        }
+    }
+}
+
+template <typename Tin, typename Tout>
+static void launch(Ctx* ctx, const void* A, const void* B, void* C, const GemmParams& p,
+                   dim3 grid, Tin* partial) {
+    const Tin* a = static_cast<const Tin*>(A);
+    const Tin* b = static_cast<const Tin*>(B);
+    Tout* c = static_cast<Tout*>(C);
+    if (p.a_kcontig && p.b_kcontig)
+        gemm_kernel<Tin, Tout, true, true><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    else if (p.a_kcontig && !p.b_kcontig)
+        gemm_kernel<Tin, Tout, true, false><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    else if (!p.a_kcontig && p.b_kcontig)
+        gemm_kernel<Tin, Tout, false, true><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    else
+        gemm_kernel<Tin, Tout, false, false><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    if (p.ksplit > 1) {
+        const int64_t tot = (int64_t)p.M * p.N * p.nprob;
+        int nb = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+        gemm_reduce_kernel<Tin, Tout><<<nb, 256, 0, ctx->stream>>>(partial, c, p);
+    }
+}
+
+void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void* C,
+          GemmParams p, int tag) {
+    FTD_CHECK(p.nprob >= 1 && p.nprob <= kMaxProbs, FTD_EINVAL, "gemm: bad problem count");
+    if (p.M <= 0 || p.N <= 0) return;
+    int nterms = 0;
+    for (int i = 0; i < p.nprob; ++i) nterms = std::max(nterms, p.prob[i].t1 - p.prob[i].t0);
+    if (p.K <= 0 || nterms == 0) {
+        FTD_CHECK(p.accumulate, FTD_EINVAL, "gemm: empty contraction without accumulate");
+        return;
+    }
+    const int tm = (p.M + GBM - 1) / GBM, tn = (p.N + GBN - 1) / GBN;
+    const int ktiles = nterms * ((p.K + GBK - 1) / GBK);
+    const int blocks = tm * tn * p.nprob;
+    int ks = 1;
+    if (blocks < 512 && ktiles >= 8) {
+        ks = (1024 + blocks - 1) / blocks;
+        ks = std::min(ks, ktiles / 4);
+        ks = std::min(ks, 64);
+        ks = std::max(ks, 1);
+    }
+    p.ksplit = ks;
+    size_t esz = (prec == Prec::F64) ? sizeof(double) : sizeof(float);
+    void* partial = nullptr;
+    if (ks > 1) {
+        size_t need = 2 * (size_t)ks * p.nprob * (size_t)p.M * p.N * esz;
+        ctx->ws_gemm_partial.ensure(ctx, need);
+        partial = ctx->ws_gemm_partial.p;
+    }
+    dim3 grid(tn, tm, p.nprob * ks);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing && tag != TAG_NONE) {
+        e0 = timing_event(ctx);
+        FTD_HIP(hipEventRecord(e0, ctx->stream));
+    }
+    if (prec == Prec::F64) {
+        FTD_CHECK(out_f64, FTD_EINVAL, "gemm: f64 inputs need f64 output");
+        launch<double, double>(ctx, A, B, C, p, grid, static_cast<double*>(partial));
+    } else if (out_f64) {
+        launch<float, double>(ctx, A, B, C, p, grid, static_cast<float*>(partial));
+    } else {
+        launch<float, float>(ctx, A, B, C, p, grid, static_cast<float*>(partial));
+    }
+    FTD_HIP(hipGetLastError());
+    if (e0) {
+        e1 = timing_event(ctx);
+        FTD_HIP(hipEventRecord(e1, ctx->stream));
+        double tot_terms = 0;
+        for (int i = 0; i < p.nprob; ++i) tot_terms += p.prob[i].t1 - p.prob[i].t0;
+        const double flops = 8.0 * p.M * (double)p.N * p.K * tot_terms;
+        const double cs = 2.0 * (double)esz;
+        const double osz = 2.0 * (out_f64 ? 8.0 : (double)esz);
+        const double bytes = tot_terms * ((double)p.M * p.K + (double)p.K * p.N) * cs +
+                             (double)p.nprob * p.M * p.N * osz * (p.accumulate ? 2.0 : 1.0);
+        // kernel identity: precision x operand layout
+        const int kind = (int)prec * 8 + (out_f64 ? 4 : 0) + p.a_kcontig * 2 + p.b_kcontig;
+        record_kernel(ctx, e0, e1, flops, bytes, tag, kind);
+    }
+}
+
+}  // namespace ftd

@@ -1,0 +1,706 @@
+// Dense factorizations on the device, float64 complex, split planes.
+//
+//  * qr_chol / lq_chol: shifted CholeskyQR in three passes for the gauge
+//    moves of the sweep (full-rank tall/wide blocks).  Every pass is a Gram
+//    GEMM, a one-workgroup Cholesky, a triangular inverse and an update
+//    GEMM; the R factors multiply to an upper factor with a real positive
+//    diagonal, i.e. the unique QR of a full-rank matrix.
+//  * qr_householder: blocked Householder QR (compact WY) for matrices of any
+//    rank; used by the compressions, where MPO x MPS products are rank
+//    deficient.  Column-major working copy; panel columns are reflected with
+//    small reduction kernels, trailing columns with GEMMs.
+//  * svd_jacobi: one-sided (Hestenes) Jacobi with a round-robin pairing, one
+//    launch per round, every column pair in its own workgroup.
+#include "common.h"
+
+#include <algorithm>
+#include <cfloat>
+#include <numeric>
+
+namespace ftd {
+
+static dim3 grid1(int64_t n, int threads = 256) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 65535 * 4) b = 65535 * 4;
+    return dim3((unsigned)b);
+}
+
+__device__ __forceinline__ double bsum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------- small dense
+// Upper Cholesky of a Hermitian n x n matrix (row-major planar, in place):
+// G = U^H U.  Optionally adds shift*I first.  flag[0] = 1 on breakdown.
+__global__ __launch_bounds__(1024) void chol_kernel(double* G, int n, int64_t plane,
+                                                    const double* shift, int* flag) {
+    __shared__ double piv;
+    const double s = shift ? shift[0] : 0.0;
+    if (s != 0.0)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) G[(int64_t)i * n + i] += s;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) {
+            const double dk = G[(int64_t)k * n + k];
+            if (!(dk > 0.0) || !isfinite(dk)) {
+                flag[0] = 1;
+                piv = 1.0;
+            } else {
+                piv = sqrt(dk);
+            }
+        }
+        __syncthreads();
+        const double p = piv;
+        // row k: U[k][j] = G[k][j] / p for j > k
+        for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
+            G[(int64_t)k * n + j] /= p;
+            G[(int64_t)k * n + j + plane] /= p;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            G[(int64_t)k * n + k] = p;
+            G[(int64_t)k * n + k + plane] = 0.0;
+        }
+        // trailing: G[i][j] -= conj(U[k][i]) U[k][j], i > k, j >= i
+        const int m = n - k - 1;
+        const int64_t tot = (int64_t)m * m;
+        for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int i = k + 1 + (int)(e / m), j = k + 1 + (int)(e % m);
+            if (j < i) continue;
+            const double ar = G[(int64_t)k * n + i], ai = -G[(int64_t)k * n + i + plane];
+            const double br = G[(int64_t)k * n + j], bi = G[(int64_t)k * n + j + plane];
+            G[(int64_t)i * n + j] -= ar * br - ai * bi;
+            G[(int64_t)i * n + j + plane] -= ar * bi + ai * br;
+        }
+        __syncthreads();
+    }
+    // clear the strictly lower part
+    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        if (j < i) {
+            G[e] = 0.0;
+            G[e + plane] = 0.0;
+        }
+    }
+}
+
+// Inverse of an upper-triangular U (row-major planar) into X; each thread
+// owns one column of X and back-substitutes.
+__global__ void triinv_kernel(const double* __restrict__ U, double* __restrict__ X, int n,
+                              int64_t plane) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int i = 0; i < n; ++i) {
+        X[(int64_t)i * n + j] = 0.0;
+        X[(int64_t)i * n + j + plane] = 0.0;
+    }
+    const double djr = U[(int64_t)j * n + j];
+    X[(int64_t)j * n + j] = 1.0 / djr;
+    for (int i = j - 1; i >= 0; --i) {
+        double sr = 0.0, si = 0.0;
+        for (int k = i + 1; k <= j; ++k) {
+            const double ur = U[(int64_t)i * n + k], ui = U[(int64_t)i * n + k + plane];
+            const double xr = X[(int64_t)k * n + j], xi = X[(int64_t)k * n + j + plane];
+            sr += ur * xr - ui * xi;
+            si += ur * xi + ui * xr;
+        }
+        const double dii = U[(int64_t)i * n + i];   // real positive
+        X[(int64_t)i * n + j] = -sr / dii;
+        X[(int64_t)i * n + j + plane] = -si / dii;
+    }
+}
+
+// trace of a Hermitian matrix -> shift = c * eps * trace
+__global__ void shift_kernel(const double* G, int n, double c, double* out) {
+    __shared__ double sh[8];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += G[(int64_t)i * n + i];
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) out[0] = c * DBL_EPSILON * s;
+}
+
+__global__ void eye_kernel(double* X, int n, int64_t plane) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        X[e] = (e / n == e % n) ? 1.0 : 0.0;
+        X[e + plane] = 0.0;
+    }
+}
+
+static GemmParams gp(int M, int N, int K) {
+    GemmParams p{};
+    p.M = M;
+    p.N = N;
+    p.K = K;
+    p.nprob = 1;
+    p.prob[0].offC = 0;
+    p.prob[0].t0 = 0;
+    p.prob[0].t1 = 1;
+    p.term[0].offA = 0;
+    p.term[0].offB = 0;
+    return p;
+}
+
+// Shifted CholeskyQR3.  wide == false: M is m x n (row-major), M = Q R.
+// wide == true: M is n x m (row-major), M = L Q with L = R^H.
+static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout, bool wide) {
+    const int64_t nn = n * n, mn = m * n;
+    ctx->ws_qr.ensure(ctx, sizeof(double) * 2 * (3 * nn + mn));
+    double* G = ctx->ws_qr.as<double>();
+    double* Xi = G + 2 * nn;
+    double* Rt = Xi + 2 * nn;
+    double* Q2 = Rt + 2 * nn;
+    double* shift = ctx->scal + 32;
+    int* flag = ctx->iscal + 8;
+    FTD_HIP(hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+    eye_kernel<<<grid1(nn), 256, 0, ctx->stream>>>(Rout, (int)n, nn);
+    for (int pass = 0; pass < 3; ++pass) {
+        // Gram matrix
+        GemmParams p = gp((int)n, (int)n, (int)m);
+        if (!wide) {
+            // G[i][j] = sum_r conj(M[r][i]) M[r][j]
+            p.sAm = 1; p.sAk = n; p.planeA = mn; p.conjA = 1; p.a_kcontig = 0;
+            p.sBk = n; p.sBn = 1; p.planeB = mn; p.b_kcontig = 0;
+        } else {
+            // G[i][j] = sum_k M[i][k] conj(M[j][k])
+            p.sAm = m; p.sAk = 1; p.planeA = mn; p.a_kcontig = 1;
+            p.sBk = 1; p.sBn = m; p.planeB = mn; p.conjB = 1; p.b_kcontig = 1;
+        }
+        p.sCm = n; p.sCn = 1; p.planeC = nn;
+        gemm(ctx, Prec::F64, true, M, M, G, p, TAG_NONE);
+        if (pass == 0) {
+            const double c = 11.0 * ((double)m * n + (double)n * (n + 1));
+            shift_kernel<<<1, 256, 0, ctx->stream>>>(G, (int)n, c, shift);
+        }
+        chol_kernel<<<1, 1024, 0, ctx->stream>>>(G, (int)n, nn, pass == 0 ? shift : nullptr, flag);
+        triinv_kernel<<<(unsigned)((n + 63) / 64), 64, 0, ctx->stream>>>(G, Xi, (int)n, nn);
+        // M <- M Xi (tall) or M <- Xi^H M (wide)
+        GemmParams q = gp(wide ? (int)n : (int)m, wide ? (int)m : (int)n, (int)n);
+        if (!wide) {
+            q.sAm = n; q.sAk = 1; q.planeA = mn; q.a_kcontig = 1;
+            q.sBk = n; q.sBn = 1; q.planeB = nn; q.b_kcontig = 0;
+            q.sCm = n; q.sCn = 1; q.planeC = mn;
+            gemm(ctx, Prec::F64, true, M, Xi, Q2, q, TAG_NONE);
+        } else {
+            // Q2[i][k] = sum_j conj(Xi[j][i]) M[j][k]
+            q.sAm = 1; q.sAk = n; q.planeA = nn; q.conjA = 1; q.a_kcontig = 0;
+            q.sBk = m; q.sBn = 1; q.planeB = mn; q.b_kcontig = 0;
+            q.sCm = m; q.sCn = 1; q.planeC = mn;
+            gemm(ctx, Prec::F64, true, Xi, M, Q2, q, TAG_NONE);
+        }
+        k_copy_f64(ctx, Q2, M, 2 * mn);
+        // R <- U_pass R
+        GemmParams r = gp((int)n, (int)n, (int)n);
+        r.sAm = n; r.sAk = 1; r.planeA = nn; r.a_kcontig = 1;
+        r.sBk = n; r.sBn = 1; r.planeB = nn; r.b_kcontig = 0;
+        r.sCm = n; r.sCn = 1; r.planeC = nn;
+        gemm(ctx, Prec::F64, true, G, Rout, Rt, r, TAG_NONE);
+        k_copy_f64(ctx, Rt, Rout, 2 * nn);
+    }
+    FTD_HIP(hipGetLastError());
+    FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
+    FTD_CHECK(ctx->h_pinned_i[0] == 0, FTD_ENOCONV,
+              "CholeskyQR breakdown: the block is numerically rank deficient");
+    if (wide) {
+        // L = R^H
+        k_transpose(ctx, Rout, n, n, nn, Rt, nn, 1);
+        k_copy_f64(ctx, Rt, Rout, 2 * nn);
+    }
+}
+
+void qr_chol(Ctx* ctx, double* M, int64_t m, int64_t n, double* R) {
+    FTD_CHECK(m >= n, FTD_EINVAL, "qr_chol: needs m >= n");
+    chol_qr_impl(ctx, M, m, n, R, false);
+}
+void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L) {
+    FTD_CHECK(m >= n, FTD_EINVAL, "lq_chol: needs m >= n");
+    chol_qr_impl(ctx, M, m, n, L, true);
+}
+
+// -------------------------------------------------------------- Householder
+// Working matrix W is column-major m x n: W[i + j*m], planar (plane = m*n).
+__global__ void hh_colnorm_partial(const double* W, int64_t m, int64_t plane, int j,
+                                   double* part) {
+    __shared__ double sh[8];
+    const double* col = W + (int64_t)j * m;
+    double s = 0.0;
+    for (int64_t i = j + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = col[i], b = col[i + plane];
+        s += a * a + b * b;
+    }
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+// reflector of column j: beta, tau, scale; W[j][j] = beta.  hs: per-column
+// record [tau_r, tau_i, scale_r, scale_i, beta]
+__global__ void hh_make(double* W, int64_t m, int64_t plane, int j, const double* part, int nb,
+                        double* hs) {
+    __shared__ double sh[8];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) {
+        const int64_t dj = (int64_t)j * m + j;
+        const double ar = W[dj], ai = W[dj + plane];
+        double* h = hs + 5 * j;
+        if (s == 0.0 && ai == 0.0) {
+            h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; h[3] = 0.0; h[4] = ar;
+        } else {
+            const double nrm = sqrt(ar * ar + ai * ai + s);
+            const double beta = ar >= 0.0 ? -nrm : nrm;
+            h[0] = (beta - ar) / beta;
+            h[1] = -ai / beta;
+            // scale = 1 / (alpha - beta)
+            const double xr = ar - beta, xi = ai;
+            const double den = xr * xr + xi * xi;
+            h[2] = xr / den;
+            h[3] = -xi / den;
+            h[4] = beta;
+            W[dj] = beta;
+            W[dj + plane] = 0.0;
+        }
+    }
+}
+__global__ void hh_scale(double* W, int64_t m, int64_t plane, int j, const double* hs) {
+    const double* h = hs + 5 * j;
+    if (h[0] == 0.0 && h[1] == 0.0) return;
+    const double sr = h[2], si = h[3];
+    double* col = W + (int64_t)j * m;
+    for (int64_t i = j + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = col[i], b = col[i + plane];
+        col[i] = a * sr - b * si;
+        col[i + plane] = a * si + b * sr;
+    }
+}
+// partial w_c = sum_{i>=j} conj(v_i) W[i][c], for c in (j, c1): grid (nb, c1-j-1)
+__global__ void hh_pdot_partial(const double* W, int64_t m, int64_t plane, int j, double* part) {
+    __shared__ double sh[8];
+    const int c = j + 1 + blockIdx.y;
+    const double* v = W + (int64_t)j * m;
+    const double* x = W + (int64_t)c * m;
+    double sr = 0.0, si = 0.0;
+    for (int64_t i = j + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double vr, vi;
+        if (i == j) {
+            vr = 1.0;
+            vi = 0.0;
+        } else {
+            vr = v[i];
+            vi = v[i + plane];
+        }
+        const double xr = x[i], xi = x[i + plane];
+        sr += vr * xr + vi * xi;
+        si += vr * xi - vi * xr;
+    }
+    sr = bsum(sr, sh);
+    si = bsum(si, sh);
+    if (threadIdx.x == 0) {
+        const int64_t o = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        part[o] = sr;
+        part[o + 1] = si;
+    }
+}
+// reduce partials (one block per column) then W[i][c] -= conj(tau) v_i w_c
+__global__ void hh_pdot_reduce(const double* part, int nb, double* wv) {
+    __shared__ double sh[8];
+    const int c = blockIdx.x;
+    double sr = 0.0, si = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        sr += part[((int64_t)c * nb + i) * 2];
+        si += part[((int64_t)c * nb + i) * 2 + 1];
+    }
+    sr = bsum(sr, sh);
+    si = bsum(si, sh);
+    if (threadIdx.x == 0) {
+        wv[2 * c] = sr;
+        wv[2 * c + 1] = si;
+    }
+}
+__global__ void hh_pupdate(double* W, int64_t m, int64_t plane, int j, int ncols,
+                           const double* wv, const double* hs) {
+    const double* h = hs + 5 * j;
+    const double tr = h[0], ti = -h[1];   // conj(tau)
+    if (h[0] == 0.0 && h[1] == 0.0) return;
+    const double* v = W + (int64_t)j * m;
+    const int64_t rows = m - j;
+    const int64_t tot = rows * ncols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int cc = (int)(e / rows);
+        const int64_t i = j + e % rows;
+        const int c = j + 1 + cc;
+        double vr, vi;
+        if (i == j) {
+            vr = 1.0;
+            vi = 0.0;
+        } else {
+            vr = v[i];
+            vi = v[i + plane];
+        }
+        const double wr = wv[2 * cc], wi = wv[2 * cc + 1];
+        // f = conj(tau) * w_c ; W -= v * f
+        const double fr = tr * wr - ti * wi, fi = tr * wi + ti * wr;
+        double* x = W + (int64_t)c * m;
+        x[i] -= vr * fr - vi * fi;
+        x[i + plane] -= vr * fi + vi * fr;
+    }
+}
+// V panel (m x pn, column-major) from W columns p0..p0+pn-1 (unit lower trapezoid)
+__global__ void hh_extract_v(const double* W, int64_t m, int64_t plane, int p0, int pn, double* V,
+                             int64_t vplane) {
+    const int64_t tot = m * pn;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / m);
+        const int64_t i = e % m;
+        const int jc = p0 + c;
+        double r = 0.0, im = 0.0;
+        if (i == jc) {
+            r = 1.0;
+        } else if (i > jc) {
+            r = W[(int64_t)jc * m + i];
+            im = W[(int64_t)jc * m + i + plane];
+        }
+        V[e] = r;
+        V[e + vplane] = im;
+    }
+}
+// T (pn x pn, row-major planar) of the compact WY form from S = V^H V:
+// T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j].  Writes both
+// T and Tn = -T^H (row-major).  Single thread: pn <= 64.
+__global__ void hh_make_t(const double* S, int pn, const double* hs, int p0, double* T,
+                          double* Tn) {
+    if (threadIdx.x != 0) return;
+    const int64_t pl = (int64_t)pn * pn;
+    for (int e = 0; e < pn * pn; ++e) {
+        T[e] = 0.0;
+        T[e + pl] = 0.0;
+    }
+    for (int j = 0; j < pn; ++j) {
+        const double tr = hs[5 * (p0 + j)], ti = hs[5 * (p0 + j) + 1];
+        for (int i = 0; i < j; ++i) {
+            double sr = 0.0, si = 0.0;
+            for (int k = i; k < j; ++k) {
+                const double ar = T[i * pn + k], ai = T[i * pn + k + pl];
+                const double br = S[k * pn + j], bi = S[k * pn + j + pl];
+                sr += ar * br - ai * bi;
+                si += ar * bi + ai * br;
+            }
+            T[i * pn + j] = -(tr * sr - ti * si);
+            T[i * pn + j + pl] = -(tr * si + ti * sr);
+        }
+        T[j * pn + j] = tr;
+        T[j * pn + j + pl] = ti;
+    }
+    for (int i = 0; i < pn; ++i)
+        for (int j = 0; j < pn; ++j) {
+            Tn[i * pn + j] = -T[j * pn + i];
+            Tn[i * pn + j + pl] = T[j * pn + i + pl];
+        }
+}
+// Q0 = [I; 0] column-major m x r
+__global__ void hh_q_init(double* Q, int64_t m, int r, int64_t plane) {
+    const int64_t tot = m * r;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / m);
+        const int64_t i = e % m;
+        Q[e] = (i == c) ? 1.0 : 0.0;
+        Q[e + plane] = 0.0;
+    }
+}
+// Output: R (r x n row-major) from W's upper part with sign fix, and
+// column signs of Q recorded in sg[j].
+__global__ void hh_extract_r(const double* W, int64_t m, int64_t plane, int r, int n,
+                             const double* hs, double* R, int64_t rplane) {
+    const int64_t tot = (int64_t)r * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        const double sg = hs[5 * i + 4] < 0.0 ? -1.0 : 1.0;
+        double a = 0.0, b = 0.0;
+        if (j >= i) {
+            a = sg * W[(int64_t)j * m + i];
+            b = sg * W[(int64_t)j * m + i + plane];
+        }
+        R[e] = a;
+        R[e + rplane] = b;
+    }
+}
+// Q column-major (m x r) -> row-major output with column sign fix
+__global__ void hh_store_q(const double* Qc, int64_t m, int r, int64_t plane, const double* hs,
+                           double* Q, int64_t qplane) {
+    const int64_t tot = m * r;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / r;
+        const int c = (int)(e % r);
+        const double sg = hs[5 * c + 4] < 0.0 ? -1.0 : 1.0;
+        Q[e] = sg * Qc[(int64_t)c * m + i];
+        Q[e + qplane] = sg * Qc[(int64_t)c * m + i + plane];
+    }
+}
+
+void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, double* R) {
+    FTD_CHECK(m >= 1 && n >= 1, FTD_EINVAL, "qr_householder: empty matrix");
+    const int r = (int)std::min(m, n);
+    const int NBP = 16;
+    const int64_t mn = m * n, mr = m * r;
+    // workspace: W (m x n), Qc (m x r), Vp (m x NBP), S/T/Tn (NBP^2 x 3), Y/Z (NBP x max(n,r)) x2
+    const int64_t wmax = std::max<int64_t>(n, r);
+    const size_t need = sizeof(double) * 2 *
+                        (mn + mr + m * NBP + 3 * NBP * NBP + 2 * NBP * wmax) +
+                        sizeof(double) * 5 * (size_t)r;
+    ctx->ws_svd3.ensure(ctx, need);
+    double* W = ctx->ws_svd3.as<double>();
+    double* Qc = W + 2 * mn;
+    double* Vp = Qc + 2 * mr;
+    double* S = Vp + 2 * m * NBP;
+    double* T = S + 2 * NBP * NBP;
+    double* Tn = T + 2 * NBP * NBP;
+    double* Y = Tn + 2 * NBP * NBP;
+    double* Z = Y + 2 * NBP * wmax;
+    double* hs = Z + 2 * NBP * wmax;
+    ctx->ws_red.ensure(ctx, sizeof(double) * 2 * 512 * (kMaxKrylov + 1));
+    double* part = ctx->ws_red.as<double>();
+    double* wv = ctx->scal + 64;   // up to NBP complex
+    // column-major copy: W = M^T storage-wise (rows m, cols n)
+    k_transpose(ctx, M, m, n, mn, W, mn, 0);
+    const int nbr = (int)std::min<int64_t>(256, std::max<int64_t>(1, (m + 2047) / 2048));
+    std::vector<int> panels;
+    for (int p0 = 0; p0 < r; p0 += NBP) panels.push_back(p0);
+    for (int p0 : panels) {
+        const int pn = std::min(NBP, r - p0);
+        for (int j = p0; j < p0 + pn; ++j) {
+            hh_colnorm_partial<<<nbr, 256, 0, ctx->stream>>>(W, m, mn, j, part);
+            hh_make<<<1, 256, 0, ctx->stream>>>(W, m, mn, j, part, nbr, hs);
+            hh_scale<<<grid1(m - j), 256, 0, ctx->stream>>>(W, m, mn, j, hs);
+            const int nc = p0 + pn - j - 1;
+            if (nc > 0) {
+                hh_pdot_partial<<<dim3(nbr, nc), 256, 0, ctx->stream>>>(W, m, mn, j, part);
+                hh_pdot_reduce<<<nc, 256, 0, ctx->stream>>>(part, nbr, wv);
+                hh_pupdate<<<grid1((m - j) * nc), 256, 0, ctx->stream>>>(W, m, mn, j, nc, wv, hs);
+            }
+        }
+        // compact WY
+        const int64_t vpl = m * pn;
+        hh_extract_v<<<grid1(m * pn), 256, 0, ctx->stream>>>(W, m, mn, p0, pn, Vp, vpl);
+        {
+            GemmParams p = gp(pn, pn, (int)m);
+            p.sAm = m; p.sAk = 1; p.planeA = vpl; p.conjA = 1; p.a_kcontig = 1;
+            p.sBk = 1; p.sBn = m; p.planeB = vpl; p.b_kcontig = 1;
+            p.sCm = pn; p.sCn = 1; p.planeC = (int64_t)pn * pn;
+            gemm(ctx, Prec::F64, true, Vp, Vp, S, p, TAG_NONE);
+        }
+        hh_make_t<<<1, 64, 0, ctx->stream>>>(S, pn, hs, p0, T, Tn);
+        const int c0 = p0 + pn, nt = (int)n - c0;
+        if (nt > 0) {
+            // Y = V^H W[:, c0:]  (pn x nt)
+            GemmParams p = gp(pn, nt, (int)m);
+            p.sAm = m; p.sAk = 1; p.planeA = vpl; p.conjA = 1; p.a_kcontig = 1;
+            p.sBk = 1; p.sBn = m; p.planeB = mn; p.b_kcontig = 1;
+            p.term[0].offB = (int64_t)c0 * m;
+            p.sCm = nt; p.sCn = 1; p.planeC = (int64_t)pn * nt;
+            gemm(ctx, Prec::F64, true, Vp, W, Y, p, TAG_NONE);
+            // Z = -T^H Y
+            GemmParams q = gp(pn, nt, pn);
+            q.sAm = pn; q.sAk = 1; q.planeA = (int64_t)pn * pn; q.a_kcontig = 1;
+            q.sBk = nt; q.sBn = 1; q.planeB = (int64_t)pn * nt; q.b_kcontig = 0;
+            q.sCm = nt; q.sCn = 1; q.planeC = (int64_t)pn * nt;
+            gemm(ctx, Prec::F64, true, Tn, Y, Z, q, TAG_NONE);
+            // W[:, c0:] += V Z
+            GemmParams u = gp((int)m, nt, pn);
+            u.sAm = 1; u.sAk = m; u.planeA = vpl; u.a_kcontig = 0;
+            u.sBk = nt; u.sBn = 1; u.planeB = (int64_t)pn * nt; u.b_kcontig = 0;
+            u.sCm = 1; u.sCn = m; u.planeC = mn; u.accumulate = 1;
+            u.prob[0].offC = (int64_t)c0 * m;
+            gemm(ctx, Prec::F64, true, Vp, Z, W, u, TAG_NONE);
+        }
+    }
+    // R
+    hh_extract_r<<<grid1((int64_t)r * n), 256, 0, ctx->stream>>>(W, m, mn, r, (int)n, hs, R,
+                                                                 (int64_t)r * n);
+    // Q = H_1 ... H_r [I; 0], applying panels last to first
+    hh_q_init<<<grid1(mr), 256, 0, ctx->stream>>>(Qc, m, r, mr);
+    for (int pi = (int)panels.size() - 1; pi >= 0; --pi) {
+        const int p0 = panels[pi];
+        const int pn = std::min(NBP, r - p0);
+        const int64_t vpl = m * pn;
+        hh_extract_v<<<grid1(m * pn), 256, 0, ctx->stream>>>(W, m, mn, p0, pn, Vp, vpl);
+        {
+            GemmParams p = gp(pn, pn, (int)m);
+            p.sAm = m; p.sAk = 1; p.planeA = vpl; p.conjA = 1; p.a_kcontig = 1;
+            p.sBk = 1; p.sBn = m; p.planeB = vpl; p.b_kcontig = 1;
+            p.sCm = pn; p.sCn = 1; p.planeC = (int64_t)pn * pn;
+            gemm(ctx, Prec::F64, true, Vp, Vp, S, p, TAG_NONE);
+        }
+        hh_make_t<<<1, 64, 0, ctx->stream>>>(S, pn, hs, p0, T, Tn);
+        // Y = V^H Q  (pn x r)
+        GemmParams p = gp(pn, r, (int)m);
+        p.sAm = m; p.sAk = 1; p.planeA = vpl; p.conjA = 1; p.a_kcontig = 1;
+        p.sBk = 1; p.sBn = m; p.planeB = mr; p.b_kcontig = 1;
+        p.sCm = r; p.sCn = 1; p.planeC = (int64_t)pn * r;
+        gemm(ctx, Prec::F64, true, Vp, Qc, Y, p, TAG_NONE);
+        // Z = -T Y : use Tn^H = -T
+        GemmParams q = gp(pn, r, pn);
+        q.sAm = 1; q.sAk = pn; q.planeA = (int64_t)pn * pn; q.conjA = 1; q.a_kcontig = 0;
+        q.sBk = r; q.sBn = 1; q.planeB = (int64_t)pn * r; q.b_kcontig = 0;
+        q.sCm = r; q.sCn = 1; q.planeC = (int64_t)pn * r;
+        gemm(ctx, Prec::F64, true, Tn, Y, Z, q, TAG_NONE);
+        // Q += V Z
+        GemmParams u = gp((int)m, r, pn);
+        u.sAm = 1; u.sAk = m; u.planeA = vpl; u.a_kcontig = 0;
+        u.sBk = r; u.sBn = 1; u.planeB = (int64_t)pn * r; u.b_kcontig = 0;
+        u.sCm = 1; u.sCn = m; u.planeC = mr; u.accumulate = 1;
+        gemm(ctx, Prec::F64, true, Vp, Z, Qc, u, TAG_NONE);
+    }
+    hh_store_q<<<grid1(mr), 256, 0, ctx->stream>>>(Qc, m, r, mr, hs, Q, mr);
+    FTD_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Jacobi
+// One round of one-sided Jacobi: pair i of round rd (circle method over n2
+// players, player n2-1 fixed).  U column-major m x n, V column-major n x n.
+__global__ __launch_bounds__(256) void jacobi_round(double* U, int64_t m, int64_t uplane,
+                                                    double* V, int n, int64_t vplane, int n2,
+                                                    int rd, double tol, int* rotated) {
+    __shared__ double sh[8];
+    __shared__ double rot[4];
+    __shared__ int skip;
+    const int i = blockIdx.x;
+    int p, q;
+    if (i == 0) {
+        p = rd % (n2 - 1);
+        q = n2 - 1;
+    } else {
+        p = (rd + i) % (n2 - 1);
+        q = (rd - i + (n2 - 1)) % (n2 - 1);
+    }
+    if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+    }
+    if (q >= n) return;   // dummy player
+    const double* x = U + (int64_t)p * m;
+    const double* y = U + (int64_t)q * m;
+    double a = 0.0, b = 0.0, cr = 0.0, ci = 0.0;
+    for (int64_t k = threadIdx.x; k < m; k += blockDim.x) {
+        const double xr = x[k], xi = x[k + uplane], yr = y[k], yi = y[k + uplane];
+        a += xr * xr + xi * xi;
+        b += yr * yr + yi * yi;
+        cr += xr * yr + xi * yi;
+        ci += xr * yi - xi * yr;
+    }
+    a = bsum(a, sh);
+    b = bsum(b, sh);
+    cr = bsum(cr, sh);
+    ci = bsum(ci, sh);
+    if (threadIdx.x == 0) {
+        const double ac = sqrt(cr * cr + ci * ci);
+        if (ac == 0.0 || ac <= tol * sqrt(a * b)) {
+            skip = 1;
+        } else {
+            skip = 0;
+            const double zeta = (b - a) / (2.0 * ac);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t);
+            const double sn = t * cs;
+            rot[0] = cs;
+            rot[1] = sn;
+            rot[2] = cr / ac;    // e^{i phi}
+            rot[3] = ci / ac;
+            rotated[i] = 1;
+        }
+    }
+    __syncthreads();
+    if (skip) return;
+    const double cs = rot[0], sn = rot[1];
+    const double er = rot[2], ei = -rot[3];   // e^{-i phi}
+    double* xw = U + (int64_t)p * m;
+    double* yw = U + (int64_t)q * m;
+    for (int64_t k = threadIdx.x; k < m; k += blockDim.x) {
+        const double xr = xw[k], xi = xw[k + uplane];
+        const double y0r = yw[k], y0i = yw[k + uplane];
+        const double yr = y0r * er - y0i * ei, yi = y0r * ei + y0i * er;   // y e^{-i phi}
+        xw[k] = cs * xr - sn * yr;
+        xw[k + uplane] = cs * xi - sn * yi;
+        yw[k] = sn * xr + cs * yr;
+        yw[k + uplane] = sn * xi + cs * yi;
+    }
+    double* vx = V + (int64_t)p * n;
+    double* vy = V + (int64_t)q * n;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const double xr = vx[k], xi = vx[k + vplane];
+        const double y0r = vy[k], y0i = vy[k + vplane];
+        const double yr = y0r * er - y0i * ei, yi = y0r * ei + y0i * er;
+        vx[k] = cs * xr - sn * yr;
+        vx[k + vplane] = cs * xi - sn * yi;
+        vy[k] = sn * xr + cs * yr;
+        vy[k + vplane] = sn * xi + cs * yi;
+    }
+}
+__global__ void count_kernel(const int* f, int n, int* out) {
+    __shared__ double sh[8];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += f[i];
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) out[0] = (int)s;
+}
+__global__ void colnorm_kernel(const double* U, int64_t m, int64_t plane, double* S) {
+    __shared__ double sh[8];
+    const double* x = U + (int64_t)blockIdx.x * m;
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < m; k += blockDim.x) s += x[k] * x[k] + x[k + plane] * x[k + plane];
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) S[blockIdx.x] = sqrt(s);
+}
+
+// X row-major m x n (m >= n).  Outputs (column-major): U m x n with columns
+// u_j * s_j (unnormalised), S[n] (unsorted), V n x n.
+void svd_jacobi(Ctx* ctx, const double* X, int64_t m, int64_t n, double* U, double* S,
+                double* V) {
+    FTD_CHECK(m >= n && n >= 1, FTD_EINVAL, "svd_jacobi: needs m >= n >= 1");
+    const int64_t mn = m * n, nn = n * n;
+    k_transpose(ctx, X, m, n, mn, U, mn, 0);
+    eye_kernel<<<grid1(nn), 256, 0, ctx->stream>>>(V, (int)n, nn);
+    if (n == 1) {
+        colnorm_kernel<<<1, 256, 0, ctx->stream>>>(U, m, mn, S);
+        FTD_HIP(hipGetLastError());
+        return;
+    }
+    const int n2 = (int)(n + (n & 1));
+    const int npair = n2 / 2;
+    const double tol = DBL_EPSILON * sqrt((double)m);
+    ctx->ws_svd2.ensure(ctx, sizeof(int) * (size_t)npair * (n2 - 1) + 64);
+    int* rotated = ctx->ws_svd2.as<int>();
+    int* cnt = ctx->iscal + 12;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        FTD_HIP(hipMemsetAsync(rotated, 0, sizeof(int) * (size_t)npair * (n2 - 1), ctx->stream));
+        for (int rd = 0; rd < n2 - 1; ++rd)
+            jacobi_round<<<npair, 256, 0, ctx->stream>>>(U, m, mn, V, (int)n, nn, n2, rd, tol,
+                                                        rotated + (size_t)rd * npair);
+        count_kernel<<<1, 256, 0, ctx->stream>>>(rotated, npair * (n2 - 1), cnt);
+        FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i + 1, cnt, sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+        if (ctx->h_pinned_i[1] == 0) break;
+        FTD_CHECK(sweep < 59, FTD_ENOCONV, "Jacobi SVD did not converge");
+    }
+    colnorm_kernel<<<(unsigned)n, 256, 0, ctx->stream>>>(U, m, mn, S);
+    FTD_HIP(hipGetLastError());
+}
+
+}  // namespace ftd

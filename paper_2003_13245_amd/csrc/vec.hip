@@ -1,0 +1,559 @@
+// Vector kernels for the Krylov exponential, the channel mixing of the MPO
+// local operators, the exact MPO x MPS product and the device-side
+// exponential of the Lanczos tridiagonal matrix.
+//
+// All reductions are deterministic: a fixed grid-stride partition, fixed
+// in-block trees, and a second pass that sums block partials in order.
+#include "common.h"
+
+#include <cfloat>
+
+namespace ftd {
+
+constexpr int RB = 256;      // threads per reduction block
+constexpr int RMAXB = 512;   // partial sums per reduction
+
+static int red_blocks(int64_t n) {
+    int64_t b = (n + RB * 8 - 1) / (RB * 8);
+    if (b < 1) b = 1;
+    if (b > RMAXB) b = RMAXB;
+    return (int)b;
+}
+
+static dim3 grid_for(int64_t n, int threads = 256, int64_t cap = 65535 * 4) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return dim3((unsigned)b);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    // wave reduction then across waves (fixed order)
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------- basic ops
+__global__ void copy_kernel(const double* __restrict__ s, double* __restrict__ d, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = s[i];
+}
+__global__ void convert_kernel(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (float)s[i];
+}
+__global__ void scale_kernel(double* x, int64_t n, int64_t plane, double re, double im) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = x[i], b = x[i + plane];
+        x[i] = re * a - im * b;
+        x[i + plane] = re * b + im * a;
+    }
+}
+// mode 0: x *= 1/sqrt(s[0]) (0 if s[0] == 0); mode 1: x *= s[0] (real)
+__global__ void scale_dev_kernel(double* x, int64_t n, int64_t plane, const double* s, int mode) {
+    double f;
+    if (mode == 0) {
+        const double q = s[0];
+        f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    } else {
+        f = s[0];
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] *= f;
+        x[i + plane] *= f;
+    }
+}
+
+void k_copy_f64(Ctx* ctx, const double* src, double* dst, int64_t n) {
+    if (n <= 0) return;
+    copy_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, dst, n);
+    FTD_HIP(hipGetLastError());
+}
+void k_convert_f64_f32(Ctx* ctx, const double* src, float* dst, int64_t n) {
+    if (n <= 0) return;
+    convert_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, dst, n);
+    FTD_HIP(hipGetLastError());
+}
+void k_scale_cplx(Ctx* ctx, double* x, int64_t n, int64_t plane, double re, double im) {
+    if (n <= 0) return;
+    scale_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(x, n, plane, re, im);
+    FTD_HIP(hipGetLastError());
+}
+void k_scale_by_dev(Ctx* ctx, double* x, int64_t n, int64_t plane, const double* s, int mode) {
+    if (n <= 0) return;
+    scale_dev_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(x, n, plane, s, mode);
+    FTD_HIP(hipGetLastError());
+}
+void k_zero(Ctx* ctx, void* p, size_t bytes) {
+    if (bytes == 0) return;
+    FTD_HIP(hipMemsetAsync(p, 0, bytes, ctx->stream));
+}
+
+// --------------------------------------------------------------- reductions
+__global__ void dot_partial(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
+                            int64_t plane, double* __restrict__ part) {
+    __shared__ double sh[8];
+    double sr = 0.0, si = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double xr = x[i], xi = x[i + plane], yr = y[i], yi = y[i + plane];
+        sr += xr * yr + xi * yi;
+        si += xr * yi - xi * yr;
+    }
+    sr = block_sum(sr, sh);
+    si = block_sum(si, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sr;
+        part[2 * blockIdx.x + 1] = si;
+    }
+}
+__global__ void nrm2_partial(const double* __restrict__ x, int64_t n, int64_t plane,
+                             double* __restrict__ part) {
+    __shared__ double sh[8];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = x[i], b = x[i + plane];
+        s += a * a + b * b;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+// sum `cnt` groups of `nb` partials, each group `width` wide (interleaved)
+__global__ void sum_partials(const double* __restrict__ part, int nb, int width, double* out) {
+    __shared__ double sh[8];
+    const int g = blockIdx.x;
+    for (int c = 0; c < width; ++c) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[((int64_t)g * nb + i) * width + c];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) out[g * width + c] = s;
+    }
+}
+
+void k_dot(Ctx* ctx, const double* x, const double* y, int64_t n, int64_t plane, double* out) {
+    const int nb = red_blocks(n);
+    ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
+    double* part = ctx->ws_red.as<double>();
+    dot_partial<<<nb, RB, 0, ctx->stream>>>(x, y, n, plane, part);
+    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 2, out);
+    FTD_HIP(hipGetLastError());
+}
+void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out) {
+    const int nb = red_blocks(n);
+    ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
+    double* part = ctx->ws_red.as<double>();
+    nrm2_partial<<<nb, RB, 0, ctx->stream>>>(x, n, plane, part);
+    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 1, out);
+    FTD_HIP(hipGetLastError());
+}
+
+// h[j] = <V_j, w>: grid (nb, k)
+__global__ void multidot_partial(const double* __restrict__ V, int64_t vstride,
+                                 const double* __restrict__ w, int64_t n, int64_t plane,
+                                 double* __restrict__ part) {
+    __shared__ double sh[8];
+    const int j = blockIdx.y;
+    const double* v = V + (int64_t)j * vstride;
+    double sr = 0.0, si = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double vr = v[i], vi = v[i + plane], wr = w[i], wi = w[i + plane];
+        sr += vr * wr + vi * wi;
+        si += vr * wi - vi * wr;
+    }
+    sr = block_sum(sr, sh);
+    si = block_sum(si, sh);
+    if (threadIdx.x == 0) {
+        const int64_t o = ((int64_t)j * gridDim.x + blockIdx.x) * 2;
+        part[o] = sr;
+        part[o + 1] = si;
+    }
+}
+void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double* w, int64_t n,
+                int64_t plane, double* h) {
+    if (k <= 0) return;
+    int nb = red_blocks(n);
+    nb = std::min(nb, 128);
+    ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
+    double* part = ctx->ws_red.as<double>();
+    multidot_partial<<<dim3(nb, k), RB, 0, ctx->stream>>>(V, vstride, w, n, plane, part);
+    sum_partials<<<k, RB, 0, ctx->stream>>>(part, nb, 2, h);
+    FTD_HIP(hipGetLastError());
+}
+
+__global__ void multiaxpy_kernel(const double* __restrict__ V, int64_t vstride, int k,
+                                 const double* __restrict__ h, double* __restrict__ w, int64_t n,
+                                 int64_t plane) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double ar = w[i], ai = w[i + plane];
+        for (int j = 0; j < k; ++j) {
+            const double hr = h[2 * j], hi = h[2 * j + 1];
+            const double vr = V[(int64_t)j * vstride + i], vi = V[(int64_t)j * vstride + i + plane];
+            ar -= vr * hr - vi * hi;
+            ai -= vr * hi + vi * hr;
+        }
+        w[i] = ar;
+        w[i + plane] = ai;
+    }
+}
+void k_multiaxpy(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h, double* w,
+                 int64_t n, int64_t plane) {
+    if (k <= 0 || n <= 0) return;
+    multiaxpy_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane);
+    FTD_HIP(hipGetLastError());
+}
+
+__global__ void lincomb_kernel(const double* __restrict__ V, int64_t vstride, int k,
+                               const double* __restrict__ u, const double* __restrict__ sc,
+                               double* __restrict__ y, int64_t n, int64_t plane) {
+    const double s = sqrt(sc[0]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double ar = 0.0, ai = 0.0;
+        for (int j = 0; j < k; ++j) {
+            const double ur = u[2 * j], ui = u[2 * j + 1];
+            const double vr = V[(int64_t)j * vstride + i], vi = V[(int64_t)j * vstride + i + plane];
+            ar += vr * ur - vi * ui;
+            ai += vr * ui + vi * ur;
+        }
+        y[i] = s * ar;
+        y[i + plane] = s * ai;
+    }
+}
+// y = sqrt(scale_dev[0]) * sum_j V_j u_j   (scale_dev holds a squared norm)
+void k_lincomb(Ctx* ctx, const double* V, int64_t vstride, int k, const double* u,
+               const double* scale_dev, double* y, int64_t n, int64_t plane) {
+    if (n <= 0) return;
+    lincomb_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(V, vstride, k, u, scale_dev, y, n, plane);
+    FTD_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ channel mixing
+template <typename Tin, typename Tout, int MAXD>
+__global__ void chanmix_kernel(const Tin* __restrict__ in, const Tin* __restrict__ ops,
+                               Tout* __restrict__ out, const MixParams p) {
+    const int d = p.d;
+    const int64_t per = (int64_t)p.Da * d * p.Db;
+    const int64_t tot = per * p.njobs;
+    const int64_t sp = (int64_t)d * p.Db;        // stride of p
+    const int64_t sa = (int64_t)d * sp;          // stride of a
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int job = (int)(e / per);
+        const int64_t r = e % per;
+        const int a = (int)(r / sp);
+        const int64_t rr = r % sp;             // q*Db + b
+        const int64_t base = a * sa + rr;
+        Tin accr[MAXD], acci[MAXD];
+#pragma unroll
+        for (int o = 0; o < MAXD; ++o) {
+            accr[o] = 0;
+            acci[o] = 0;
+        }
+        for (int en = p.job[job].e0; en < p.job[job].e1; ++en) {
+            const Tin* x = in + p.ent[en].offIn + base;
+            const Tin* opr = ops + (int64_t)p.ent[en].op * p.opStride;
+            const Tin* opi = opr + (int64_t)d * d;
+            for (int pp = 0; pp < d; ++pp) {
+                const Tin xr = x[pp * sp], xi = x[pp * sp + p.planeIn];
+#pragma unroll
+                for (int o = 0; o < MAXD; ++o) {
+                    if (o < d) {
+                        const Tin orr = opr[o * d + pp], oi = opi[o * d + pp];
+                        accr[o] += orr * xr - oi * xi;
+                        acci[o] += orr * xi + oi * xr;
+                    }
+                }
+            }
+        }
+        Tout* y = out + p.job[job].offOut + base;
+#pragma unroll
+        for (int o = 0; o < MAXD; ++o) {
+            if (o < d) {
+                if (p.accumulate) {
+                    y[o * sp] += (Tout)accr[o];
+                    y[o * sp + p.planeOut] += (Tout)acci[o];
+                } else {
+                    y[o * sp] = (Tout)accr[o];
+                    y[o * sp + p.planeOut] = (Tout)acci[o];
+                }
+            }
+        }
+    }
+}
+
+template <typename Tin, typename Tout>
+static void chanmix_t(Ctx* ctx, const void* in, const void* ops, void* out, const MixParams& p) {
+    const int64_t tot = (int64_t)p.Da * p.d * p.Db * p.njobs;
+    if (tot <= 0) return;
+    dim3 g = grid_for(tot);
+    const Tin* a = static_cast<const Tin*>(in);
+    const Tin* o = static_cast<const Tin*>(ops);
+    Tout* y = static_cast<Tout*>(out);
+    if (p.d <= 2)
+        chanmix_kernel<Tin, Tout, 2><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
+    else if (p.d <= 4)
+        chanmix_kernel<Tin, Tout, 4><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
+    else if (p.d <= 8)
+        chanmix_kernel<Tin, Tout, 8><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
+    else if (p.d <= 16)
+        chanmix_kernel<Tin, Tout, 16><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
+    else
+        chanmix_kernel<Tin, Tout, 32><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
+    FTD_HIP(hipGetLastError());
+}
+
+void chanmix(Ctx* ctx, Prec prec, bool out_f64, const void* in, const void* ops, void* out,
+             const MixParams& p) {
+    FTD_CHECK(p.d <= 32, FTD_EINVAL, "local dimension above 32 is not supported");
+    if (p.njobs == 0) return;
+    if (prec == Prec::F64)
+        chanmix_t<double, double>(ctx, in, ops, out, p);
+    else if (out_f64)
+        chanmix_t<float, double>(ctx, in, ops, out, p);
+    else
+        chanmix_t<float, float>(ctx, in, ops, out, p);
+}
+
+// ------------------------------------------------------ MPO x MPS, embedding
+__global__ void mpo_apply_kernel(const double* __restrict__ A, int Da, int d, int Db,
+                                 const double* __restrict__ ops, int64_t opStride, int wl, int wr,
+                                 const ApplyEnt* __restrict__ ents, int nents,
+                                 double* __restrict__ B) {
+    const int64_t per = (int64_t)Da * d * Db;   // (a, q, b)
+    const int64_t tot = per * nents;
+    const int64_t nA = (int64_t)Da * d * d * Db;
+    const int64_t DA = (int64_t)Da * wl, DB = (int64_t)Db * wr;
+    const int64_t nB = DA * d * d * DB;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int en = (int)(e / per);
+        const int64_t r = e % per;
+        const int a = (int)(r / ((int64_t)d * Db));
+        const int q = (int)((r / Db) % d);
+        const int b = (int)(r % Db);
+        const ApplyEnt E = ents[en];
+        const double* opr = ops + (int64_t)E.op * opStride;
+        const double* opi = opr + (int64_t)d * d;
+        const int64_t ar = (int64_t)a * wl + E.cl, bc = (int64_t)b * wr + E.cr;
+        for (int P = 0; P < d; ++P) {
+            double sr = 0.0, si = 0.0;
+            for (int pp = 0; pp < d; ++pp) {
+                const int64_t ia = (((int64_t)a * d + pp) * d + q) * Db + b;
+                const double xr = A[ia], xi = A[ia + nA];
+                const double orr = opr[P * d + pp], oi = opi[P * d + pp];
+                sr += orr * xr - oi * xi;
+                si += orr * xi + oi * xr;
+            }
+            const int64_t ib = ((ar * d + P) * d + q) * DB + bc;
+            B[ib] = sr;
+            B[ib + nB] = si;
+        }
+    }
+}
+void k_mpo_apply(Ctx* ctx, const double* A, int Da, int d, int Db, const double* ops,
+                 int64_t opStride, int wl, int wr, const ApplyEnt* ents_dev, int nents,
+                 double* B) {
+    const int64_t nB = (int64_t)Da * wl * d * d * Db * wr;
+    k_zero(ctx, B, sizeof(double) * 2 * nB);
+    const int64_t tot = (int64_t)Da * d * Db * nents;
+    if (tot <= 0) return;
+    mpo_apply_kernel<<<grid_for(tot), 256, 0, ctx->stream>>>(A, Da, d, Db, ops, opStride, wl, wr,
+                                                              ents_dev, nents, B);
+    FTD_HIP(hipGetLastError());
+}
+
+__global__ void embed_kernel(const double* __restrict__ src, int Da, int dd, int Db,
+                             double* __restrict__ dst, int DA, int DB, int a0, int b0, double re,
+                             double im) {
+    const int64_t n = (int64_t)Da * dd * Db;
+    const int64_t N = (int64_t)DA * dd * DB;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e / ((int64_t)dd * Db));
+        const int s = (int)((e / Db) % dd);
+        const int b = (int)(e % Db);
+        const double xr = src[e], xi = src[e + n];
+        const int64_t o = (((int64_t)(a + a0)) * dd + s) * DB + (b + b0);
+        dst[o] = re * xr - im * xi;
+        dst[o + N] = re * xi + im * xr;
+    }
+}
+void k_embed(Ctx* ctx, const double* src, int Da, int dd, int Db, double* dst, int DA, int DB,
+             int a0, int b0, double re, double im) {
+    const int64_t n = (int64_t)Da * dd * Db;
+    if (n <= 0) return;
+    embed_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, Da, dd, Db, dst, DA, DB, a0, b0, re, im);
+    FTD_HIP(hipGetLastError());
+}
+
+__global__ void transpose_kernel(const double* __restrict__ s, int64_t rows, int64_t cols,
+                                 int64_t splane, double* __restrict__ d, int64_t dplane, int conj) {
+    __shared__ double tr[32][33], ti[32][33];
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) {
+            tr[k][tx] = s[r * cols + c];
+            ti[k][tx] = s[r * cols + c + splane];
+        }
+    }
+    __syncthreads();
+    const double sg = conj ? -1.0 : 1.0;
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = c0 + k, r = r0 + tx;   // dst row = c, dst col = r
+        if (r < rows && c < cols) {
+            d[c * rows + r] = tr[tx][k];
+            d[c * rows + r + dplane] = sg * ti[tx][k];
+        }
+    }
+}
+void k_transpose(Ctx* ctx, const double* src, int64_t rows, int64_t cols, int64_t splane,
+                 double* dst, int64_t dplane, int conj) {
+    if (rows <= 0 || cols <= 0) return;
+    dim3 g((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+    transpose_kernel<<<g, 256, 0, ctx->stream>>>(src, rows, cols, splane, dst, dplane, conj);
+    FTD_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------ Krylov: tridiagonal
+// Exponential of the n x n Lanczos matrix T (diag alpha, off-diagonal beta)
+// applied to e_1, by the implicit QL algorithm with Wilkinson shifts (one
+// wavefront: lane j owns row j of the eigenvector matrix; the scalar
+// recurrences are evaluated identically in every lane and exchanged by
+// lane reads).  Also records beta_{n-1} = |w| and the convergence decision.
+__device__ __forceinline__ double lane_get(double v, int i) { return __shfl(v, i, 64); }
+
+__global__ __launch_bounds__(64) void tridiag_expm_kernel(KrylovDev kd, int n, double zr,
+                                                          double zi, double tol, int exhausted,
+                                                          int mmax) {
+    __shared__ double Z[kMaxKrylov][kMaxKrylov + 1];
+    const int j = threadIdx.x;
+    const double bnew = sqrt(fmax(kd.nrm[0], 0.0));
+    double dj = (j < n) ? kd.alpha[j] : 0.0;
+    double ej = (j < n - 1) ? kd.beta[j] : 0.0;
+    for (int i = 0; i < n; ++i) Z[j][i] = (i == j) ? 1.0 : 0.0;
+    int fail = 0;
+    for (int l = 0; l < n && !fail; ++l) {
+        int iter = 0;
+        while (true) {
+            int m;
+            for (m = l; m < n - 1; ++m) {
+                const double dd = fabs(lane_get(dj, m)) + fabs(lane_get(dj, m + 1));
+                if (fabs(lane_get(ej, m)) <= DBL_EPSILON * dd) break;
+            }
+            if (m == l) break;
+            if (iter++ == 60) {
+                fail = 1;
+                break;
+            }
+            const double dl = lane_get(dj, l), el = lane_get(ej, l);
+            double g = (lane_get(dj, l + 1) - dl) / (2.0 * el);
+            double r = hypot(g, 1.0);
+            g = lane_get(dj, m) - dl + el / (g + copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool early = false;
+            for (int i = m - 1; i >= l; --i) {
+                const double ei = lane_get(ej, i);
+                const double f = s * ei, b = c * ei;
+                r = hypot(f, g);
+                if (j == i + 1) ej = r;
+                if (r == 0.0) {
+                    const double v = lane_get(dj, i + 1) - p;
+                    if (j == i + 1) dj = v;
+                    if (j == m) ej = 0.0;
+                    early = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = lane_get(dj, i + 1) - p;
+                r = (lane_get(dj, i) - g) * s + 2.0 * c * b;
+                p = s * r;
+                if (j == i + 1) dj = g + p;
+                g = c * r - b;
+                const double zf = Z[j][i + 1], zi0 = Z[j][i];
+                Z[j][i + 1] = s * zi0 + c * zf;
+                Z[j][i] = c * zi0 - s * zf;
+            }
+            if (early) continue;
+            const double v = lane_get(dj, l) - p;
+            if (j == l) {
+                dj = v;
+                ej = g;
+            }
+            if (j == m) ej = 0.0;
+        }
+    }
+    __syncthreads();
+    // u_j = sum_i Z[j][i] exp(z lambda_i) Z[0][i]
+    double ur = 0.0, ui = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double lam = lane_get(dj, i);
+        const double mag = exp(zr * lam);
+        const double er = mag * cos(zi * lam), ei = mag * sin(zi * lam);
+        const double w0 = Z[0][i];
+        const double zz = (j < n) ? Z[j][i] : 0.0;
+        ur += zz * er * w0;
+        ui += zz * ei * w0;
+    }
+    double nn = (j < n) ? ur * ur + ui * ui : 0.0;
+    for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
+    const double ulr = lane_get(ur, n - 1), uli = lane_get(ui, n - 1);
+    const double err = bnew * sqrt(ulr * ulr + uli * uli);
+    if (j < n) {
+        kd.u[2 * j] = ur;
+        kd.u[2 * j + 1] = ui;
+    }
+    if (j == 0) {
+        kd.beta[n - 1] = bnew;
+        const bool finite = isfinite(nn) && isfinite(bnew);
+        const int conv = (exhausted || err <= tol * sqrt(nn) || bnew == 0.0) ? 1 : 0;
+        kd.flag[0] = (finite && !fail) ? conv : 0;
+        kd.flag[1] = n;
+        kd.flag[2] = (!finite || fail || (!conv && n >= mmax)) ? 1 : 0;
+    }
+}
+
+// w /= beta_{n-1} unless converged
+__global__ void lanczos_post_kernel(KrylovDev kd, int n, double* w, int64_t len, int64_t plane) {
+    if (kd.flag[0] || kd.flag[2]) return;
+    const double b = kd.beta[n - 1];
+    const double f = 1.0 / b;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        w[i] *= f;
+        w[i + plane] *= f;
+    }
+}
+__global__ void set_alpha_kernel(KrylovDev kd, int k) { kd.alpha[k] = kd.h[2 * k]; }
+
+void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
+                    int exhausted) {
+    tridiag_expm_kernel<<<1, 64, 0, ctx->stream>>>(kd, k, zr, zi, tol, exhausted, kMaxKrylov);
+    FTD_HIP(hipGetLastError());
+}
+void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane) {
+    lanczos_post_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(kd, k, w, n, plane);
+    FTD_HIP(hipGetLastError());
+}
+void k_set_alpha(Ctx* ctx, KrylovDev kd, int k) {
+    set_alpha_kernel<<<1, 1, 0, ctx->stream>>>(kd, k);
+    FTD_HIP(hipGetLastError());
+}
+
+}  // namespace ftd
