@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of the finite-temperature TD-DMRG correlation loop on one GPU.
+
+Workload: the rubrene-shaped Holstein-Peierls ring (21 molecules, 4 local
+modes per molecule and 1 bond mode per bond, 10 phonon levels, purified MPS
+bond dimension 128, T = 300 K), synthetic seeded parameters.
+
+A step is one step of the C(t) loop: one second-order one-site TDVP step of
+Psi_beta, one of j Psi_beta, and the overlap <Psi|j|Phi>.  The inputs
+(Psi_beta from the imaginary-time preparation and j Psi_beta compressed to
+D) are prepared before the timed region and stay resident in HBM.  The
+headline value is the mixed-precision path (complex64 contractions on MFMA,
+float64 Krylov/QR/norms); the same steps are then repeated in float64 from
+the same inputs, which gives the speedup and the C(t) error of the mixed path.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "TDVP steps/s + H_eff TFLOP/s, mixed vs FP64 at C(t) rel err 1e-4, D=128"
+PEAK = {"c64": 157.3, "c128": 78.6, "bf16x3": 2516.6}   # TFLOP/s, dense MFMA
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2003_13245_amd import workloads as W
+    if name == "headline":
+        return W.headline()
+    if name == "small":
+        return W.rubrene_shaped(n_mol=5, n_loc=2, n_nl=1, levels=6, D=32, n_imag=8)
+    if name == "medium":
+        return W.rubrene_shaped(n_mol=11, n_loc=4, n_nl=1, levels=10, D=64, n_imag=16)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_steps(api, ctx, H, J, psi0, phi0, steps, dt, tol, mmax, timing):
+    psi, phi = psi0.copy(), phi0.copy()
+    C = []
+    ctx.stats_reset()
+    ctx.set_timing(timing)
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.tdvp_step(ctx, H, psi, dt_real=dt, tol=tol, mmax=mmax)
+        api.tdvp_step(ctx, H, phi, dt_real=dt, tol=tol, mmax=mmax)
+        C.append(api.overlap(ctx, psi, J, phi))
+    ctx.synchronize()
+    t1 = time.perf_counter()
+    st = ctx.stats()
+    ctx.set_timing(False)
+    return np.array(C), t1 - t0, st
+
+
+def cpu_baseline(wl, matvecs_per_step, budget_s=20.0):
+    """Oracle H_eff matvecs at the workload's widest phonon-site shape (random
+    environments of the oracle MPO's channel count), scaled to a step by the
+    number of matvecs one step issued on the GPU."""
+    from oracle import mpo as OM
+    from oracle import tdvp as T
+    m = wl.model
+    Hw = OM.hamiltonian_mpo(m)
+    D = wl.run.D
+    L = len(Hw)
+    site = next(i for i in range(L // 2, L) if Hw[i].shape[2] > 2)
+    W = Hw[site]
+    d = W.shape[2]
+    rng = np.random.default_rng(0)
+    Lenv = rng.standard_normal((W.shape[0], D, D)) + 1j * rng.standard_normal((W.shape[0], D, D))
+    Renv = rng.standard_normal((W.shape[1], D, D)) + 1j * rng.standard_normal((W.shape[1], D, D))
+    A = rng.standard_normal((D, d, d, D)) + 1j * rng.standard_normal((D, d, d, D))
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    n, t0 = 0, time.perf_counter()
+    while True:
+        T.heff_apply(Lenv, W, Renv, A)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 50:
+            break
+    per = el / n
+    step_s = per * matvecs_per_step
+    return {"value": 1.0 / step_s, "unit": "pair-steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} oracle H_eff matvecs at the D={D}, d={d} phonon-site shape "
+                      f"({per:.3f} s each, {el:.1f} s total), scaled by the "
+                      f"{matvecs_per_step:.0f} matvecs of one GPU step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="headline")
+    ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--krylov-tol", type=float, default=1e-10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2003_13245_amd import api
+
+    wl = workload(args.workload)
+    m, r = wl.model, wl.run
+    ctx = api.Context(0)
+    H, J = api.mpo_build(ctx, m)
+    tol, mmax = args.krylov_tol, 40
+
+    log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D})")
+    t0 = time.perf_counter()
+    psi_beta, logz = api.thermal_prep(ctx, H, r.beta, r.n_imag, -1, r.D, cutoff=r.cutoff,
+                                      precision=args.precision, tol=tol, mmax=mmax)
+    t_prep = time.perf_counter() - t0
+    log(f"[bench] prep {t_prep:.1f} s, ln Z = {logz:.6f}, bonds max {max(psi_beta.info()['bond_dims'])}")
+    t0 = time.perf_counter()
+    phi0 = api.apply_compress(ctx, J, psi_beta, r.D, r.cutoff)
+    t_j = time.perf_counter() - t0
+    log(f"[bench] j|Psi> compressed in {t_j:.1f} s")
+    psi0 = psi_beta
+
+    # warmup (untimed), then the timed mixed-precision steps
+    if args.warmup:
+        run_steps(api, ctx, H, J, psi0, phi0, args.warmup, r.dt, tol, mmax, False)
+    C_mix, el_mix, st = run_steps(api, ctx, H, J, psi0, phi0, args.steps, r.dt, tol, mmax, True)
+    sps = args.steps / el_mix
+    log(f"[bench] mixed: {el_mix / args.steps * 1e3:.1f} ms/step, H_eff "
+        f"{st['heff_flops'] / max(st['heff_ms'], 1e-9) / 1e9:.1f} TFLOP/s")
+
+    out = {
+        "metric": METRIC, "value": sps, "unit": "pair-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el_mix / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": wl.name, "n_mol": m.n_mol, "local_modes": m.n_loc,
+                   "bond_modes": m.n_nl, "levels": m.levels_loc, "D": r.D,
+                   "T_K": 300.0, "dt_fs": 0.5, "krylov_tol": tol},
+        "heff_tflops": st["heff_flops"] / max(st["heff_ms"], 1e-9) / 1e9,
+        "matvecs_per_step": st["matvecs"] / args.steps,
+        "krylov_mean": st["krylov_vectors"] / max(st["expm_calls"], 1),
+        "prep_s": t_prep, "jcompress_s": t_j,
+    }
+    dom_avg_ms = st["dom_ms"] / max(st["dom_launches"], 1)
+    achieved = st["dom_flops"] / max(st["dom_ms"], 1e-12) / 1e9     # TFLOP/s
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision],
+                       "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
+                       "traffic": None, "kernel": "gemm_kernel (H_eff contraction)",
+                       "avg_launch_ms": dom_avg_ms, "launches": st["dom_launches"]}
+    if not args.no_fp64:
+        C64, el64, st64 = run_steps(api, ctx, H, J, _as(api, ctx, psi0, "c128"),
+                                    _as(api, ctx, phi0, "c128"), args.steps, r.dt, 1e-12,
+                                    mmax, True)
+        out["fp64_steps_per_s"] = args.steps / el64
+        out["speedup_vs_fp64"] = sps / out["fp64_steps_per_s"]
+        out["fp64_heff_tflops"] = st64["heff_flops"] / max(st64["heff_ms"], 1e-9) / 1e9
+        out["c_rel_err_vs_fp64"] = float(np.abs(C_mix - C64).max() /
+                                         abs(api.overlap(ctx, psi0, J, phi0)))
+        log(f"[bench] fp64: {el64 / args.steps * 1e3:.1f} ms/step; C(t) rel err "
+            f"{out['c_rel_err_vs_fp64']:.2e}")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, out["matvecs_per_step"])
+    print(json.dumps(out), flush=True)
+
+
+def _as(api, ctx, psi, precision):
+    """A copy of psi whose contractions run in `precision`."""
+    c = psi.copy()
+    c.set_precision(precision)
+    return c
+
+
+if __name__ == "__main__":
+    main()

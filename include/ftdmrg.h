@@ -160,6 +160,9 @@ ftd_status ftd_mps_get_site(ftd_ctx* ctx, const ftd_mps* psi, int32_t site, doub
 ftd_status ftd_mps_from_host(ftd_ctx* ctx, int32_t n_sites, const int32_t* dims,
                              const double* host, double log_norm, ftd_precision prec,
                              ftd_mps** out);
+/* Select the arithmetic of the contractions applied to psi from now on
+ * (site tensors stay float64).  Errors: FTD_EINVAL for an unknown precision. */
+ftd_status ftd_mps_set_precision(ftd_mps* psi, ftd_precision prec);
 /* <psi|psi> of the tensors (log_norm excluded), float64. */
 ftd_status ftd_mps_norm(ftd_ctx* ctx, const ftd_mps* psi, double* out);
 
@@ -193,6 +196,14 @@ ftd_status ftd_tdvp_step(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt
 ftd_status ftd_apply_compress(ftd_ctx* ctx, const ftd_mpo* O, const ftd_mps* psi, int32_t D,
                               double cutoff, ftd_mps** out);
 
+/* One propagation-and-compression stage of the bond growth:
+ * out = compress(psi + c O phi, D) by zip-up (left-to-right SVD truncation
+ * of the partial products to 2D, then a right-to-left sweep to D, keeping
+ * s/s_max > cutoff).  psi and phi must carry the same log_norm; c is complex
+ * (c[0] + i c[1]).  out belongs to the caller. */
+ftd_status ftd_pc_stage(ftd_ctx* ctx, const ftd_mps* psi, const ftd_mpo* O, const ftd_mps* phi,
+                        const double* c, int32_t D, double cutoff, ftd_mps** out);
+
 /* <bra| O |ket> (log_norm factors excluded), complex, host out[2]. */
 ftd_status ftd_overlap(ftd_ctx* ctx, const ftd_mps* bra, const ftd_mpo* O, const ftd_mps* ket,
                        double* out);
@@ -221,6 +232,15 @@ ftd_status ftd_mobility(const double* C, int32_t n, double dt, double beta, doub
  * roofline measurement. */
 ftd_status ftd_heff_apply(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, int32_t site,
                           const double* x, double* y, int32_t n_repeat);
+
+/* Truncated SVD on the device (the compression kernel): T (M x N, host,
+ * interleaved complex, row-major) ~ L diag(S) R with L (M x k) orthonormal
+ * columns and R (k x N) orthonormal rows, keeping at most D singular values
+ * with s/s_max > cutoff and whole near-degenerate multiplets.  S is folded
+ * into L (s_left = 1) or R (s_left = 0).  L and R are host buffers of at
+ * least M*min(M,N) and min(M,N)*N complex values; *k receives the rank. */
+ftd_status ftd_svd_trunc(ftd_ctx* ctx, int32_t M, int32_t N, const double* T, int32_t D,
+                         double cutoff, int32_t s_left, double* L, double* R, int32_t* k);
 
 /* Complex GEMM on the device kernels: C = op(A) op(B) with op = identity,
  * transpose or conjugate transpose per operand (trans = 0, 1, 2), M x N

@@ -17,10 +17,10 @@ Site tensors are A[a, p, q, b] (left bond, P leg, Q leg, right bond).
 Readings where the paper is silent (they bind the HIP path too):
   * bond growth: the first n_grow imaginary steps are taken by
     propagation-and-compression with a fourth-order Taylor polynomial of
-    exp(-dtau H) in Horner form, each stage an exact MPO x MPS product plus a
-    sum, compressed by a left QR sweep and a right-to-left SVD sweep keeping
-    at most D singular values with s/s_max > cutoff and never splitting a
-    multiplet whose relative gap is below 1e-8;
+    exp(-dtau H) in Horner form, each stage psi + c H phi formed exactly and
+    SVD-compressed (exact right-canonical form, then a left-to-right sweep
+    keeping at most D singular values with s/s_max > cutoff, never splitting
+    a multiplet whose relative gap is below 1e-8);
   * the remaining imaginary steps and all real-time steps are one-site TDVP
     sweeps: left-to-right with half step, then right-to-left with half step,
     the last site evolved twice, the bond matrix evolved backwards;
@@ -28,8 +28,8 @@ Readings where the paper is silent (they bind the HIP path too):
   * Krylov exponential: Lanczos with full (twice-applied classical
     Gram-Schmidt) reorthogonalisation; stop when beta_k |e_k^T exp(zT_k) e_1|
     <= tol |exp(zT_k) e_1|, or when the Krylov space is exhausted;
-  * j|Psi_b> is compressed to the same D with the same rule and keeps the norm
-    the truncation leaves.
+  * j|Psi_b> is compressed to the same D by the same SVD compression and
+    keeps the norm the truncation leaves.
 """
 from __future__ import annotations
 
@@ -212,23 +212,50 @@ def add(psi, phi, c):
     return MPS(out, psi.log_norm)
 
 
-def compress(psi, D, cutoff):
-    """Left QR sweep, then right-to-left SVD truncation.  Returns a
-    right-canonical MPS whose first tensor carries the norm."""
-    A = [a.copy() for a in psi.A]
+def right_canonicalize(A):
+    """LQ sweep from the right without truncation (in place on a list)."""
+    for i in range(len(A) - 1, 0, -1):
+        a, d, _, b = A[i].shape
+        Lm, Q = lq_pos(A[i].reshape(a, d * d * b))
+        A[i] = Q.reshape(Q.shape[0], d, d, b)
+        A[i - 1] = np.tensordot(A[i - 1], Lm, axes=([3], [0]))
+    return A
+
+
+def svd_compress(X, D, cutoff):
+    """SVD compression of an MPS: bring it to right-canonical form exactly,
+    then sweep left to right truncating each bond to at most D singular
+    values with s/s_max > cutoff (whole multiplets), then return it to
+    right-canonical form.  The result depends only on the state, not on how
+    the input tensors are gauged or which MPO produced them."""
+    A = right_canonicalize([t.copy() for t in X.A])
     L = len(A)
     for i in range(L - 1):
         a, d, _, b = A[i].shape
-        Q, R = qr_pos(A[i].reshape(a * d * d, b))
-        A[i] = Q.reshape(a, d, d, Q.shape[1])
-        A[i + 1] = np.tensordot(R, A[i + 1], axes=([1], [0]))
-    for i in range(L - 1, 0, -1):
-        a, d, _, b = A[i].shape
-        U, s, Vh = np.linalg.svd(A[i].reshape(a, d * d * b), full_matrices=False)
+        U, s, Vh = np.linalg.svd(A[i].reshape(a * d * d, b), full_matrices=False)
         k = truncation_rank(s, D, cutoff)
-        A[i] = Vh[:k].reshape(k, d, d, b)
-        A[i - 1] = np.tensordot(A[i - 1], U[:, :k] * s[None, :k], axes=([3], [0]))
-    return MPS(A, psi.log_norm)
+        A[i] = U[:, :k].reshape(a, d, d, k)
+        A[i + 1] = np.tensordot(s[:k, None] * Vh[:k], A[i + 1], axes=([1], [0]))
+    return MPS(right_canonicalize(A), X.log_norm)
+
+
+def compress_terms(terms, D, cutoff):
+    """Compressed sum_t c_t O_t |psi_t> (O_t an MPO or None for the
+    identity): the exact sum is formed and SVD-compressed."""
+    X = None
+    for c, Ws, p in terms:
+        Y = apply_mpo(Ws, p) if Ws is not None else p.copy()
+        if X is None:
+            Y.A[0] = c * Y.A[0]
+            X = Y
+        else:
+            X = add(X, Y, c)
+    return svd_compress(X, D, cutoff)
+
+
+def compress(psi, D, cutoff):
+    """SVD compression of a single MPS."""
+    return svd_compress(psi, D, cutoff)
 
 
 def normalize(psi):
@@ -245,8 +272,7 @@ def taylor_growth_step(psi, Hw, dtau, D, cutoff, order=4):
     Horner form: phi <- psi + (-dtau/k) H phi, k = order..1."""
     phi = psi
     for k in range(order, 0, -1):
-        Hphi = apply_mpo(Hw, phi)
-        phi = compress(add(psi, Hphi, -dtau / k), D, cutoff)
+        phi = compress_terms([(1.0, None, psi), (-dtau / k, Hw, phi)], D, cutoff)
     return phi
 
 
@@ -443,7 +469,7 @@ def thermal_prep(model, Hw, beta, n_imag, n_grow, D, cutoff=1e-10, tol=1e-14,
 
 def apply_current(Jw, psi, D, cutoff=1e-10):
     """j|psi> compressed to bond dimension D (norm kept, log_norm reset)."""
-    phi = compress(apply_mpo(Jw, psi), D, cutoff)
+    phi = compress_terms([(1.0, Jw, psi)], D, cutoff)
     phi.log_norm = 0.0
     return phi
 

@@ -77,18 +77,28 @@ SIGNATURES = {
     "ftd_mps_get_site": (I32, [P, P, I32, DP, C.c_int64]),
     "ftd_mps_from_host": (I32, [P, I32, I32P, DP, D, I32, PP]),
     "ftd_mps_norm": (I32, [P, P, DP]),
+    "ftd_mps_set_precision": (I32, [P, I32]),
     "ftd_thermal_prep": (I32, [P, P, D, I32, I32, I32, D, I32, C.POINTER(KrylovOpts), PP, DP]),
     "ftd_tdvp_step": (I32, [P, P, P, D, D, C.POINTER(KrylovOpts)]),
     "ftd_apply_compress": (I32, [P, P, P, I32, D, PP]),
     "ftd_overlap": (I32, [P, P, P, P, DP]),
+    "ftd_pc_stage": (I32, [P, P, P, P, DP, I32, D, PP]),
     "ftd_corr_current": (I32, [P, P, P, P, I32, D, D, I32, C.POINTER(KrylovOpts), DP]),
     "ftd_mobility": (I32, [DP, I32, D, D, D, DP, DP]),
     "ftd_heff_apply": (I32, [P, P, P, I32, DP, DP, I32]),
+    "ftd_svd_trunc": (I32, [P, I32, I32, DP, I32, D, I32, DP, DP, I32P]),
     "ftd_gemm": (I32, [P, I32, I32, I32, I32, I32, I32, DP, DP, DP]),
 }
 
 
 def _load():
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # loading torch first makes this library bind to that single runtime, so
+    # torch streams and allocations are valid handles here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2003_13245_amd.build.build()")
     lib = C.CDLL(LIB_PATH)

@@ -8,12 +8,23 @@ built: importing this module raises ImportError otherwise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 
 import numpy as np
 
 from . import _abi
 from ._abi import FtdError, PRECISION, check, lib
+
+_SHUTDOWN = [False]
+
+
+@atexit.register
+def _mark_shutdown():
+    # Native handles are released with the process; destroying them while the
+    # interpreter (and torch's allocator) tears down is not safe.
+    _SHUTDOWN[0] = True
+
 
 __all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step",
            "corr_current", "mobility", "apply_compress", "overlap", "heff_apply",
@@ -65,7 +76,7 @@ class Context:
 
     def __del__(self):
         try:
-            if getattr(self, "h", None):
+            if getattr(self, "h", None) and not _SHUTDOWN[0]:
                 lib.ftd_ctx_destroy(self.h)
                 self.h = None
         except Exception:
@@ -101,7 +112,7 @@ class Mpo:
 
     def __del__(self):
         try:
-            if self.h:
+            if self.h and not _SHUTDOWN[0]:
                 lib.ftd_mpo_destroy(self.h)
                 self.h = None
         except Exception:
@@ -134,6 +145,9 @@ class Mps:
         check(lib.ftd_mps_copy(self.ctx.h, self.h, C.byref(h)))
         return Mps(self.ctx, h)
 
+    def set_precision(self, precision: str):
+        check(lib.ftd_mps_set_precision(self.h, PRECISION[precision]))
+
     def norm2(self) -> float:
         out = C.c_double()
         check(lib.ftd_mps_norm(self.ctx.h, self.h, C.byref(out)))
@@ -141,7 +155,7 @@ class Mps:
 
     def __del__(self):
         try:
-            if self.h:
+            if self.h and not _SHUTDOWN[0]:
                 lib.ftd_mps_destroy(self.h)
                 self.h = None
         except Exception:
@@ -192,6 +206,15 @@ def tdvp_step(ctx, H, psi, dt_real=0.0, dt_imag=0.0, tol=1e-14, mmax=40):
 def apply_compress(ctx, O, psi, D, cutoff=1e-10):
     out = C.c_void_p()
     check(lib.ftd_apply_compress(ctx.h, O.h, psi.h, int(D), float(cutoff), C.byref(out)))
+    return Mps(ctx, out)
+
+
+def pc_stage(ctx, psi, O, phi, c, D, cutoff=1e-10):
+    """compress(psi + c O phi, D): one propagation-and-compression stage."""
+    cc = np.array([complex(c).real, complex(c).imag])
+    out = C.c_void_p()
+    check(lib.ftd_pc_stage(ctx.h, psi.h, O.h, phi.h, _abi._dptr(cc), int(D), float(cutoff),
+                           C.byref(out)))
     return Mps(ctx, out)
 
 
@@ -252,6 +275,23 @@ def gemm(ctx, A, B, transA=0, transB=0, precision="c128"):
     check(lib.ftd_gemm(ctx.h, PRECISION[precision], M, N, K, int(transA), int(transB),
                        _abi._dptr(ab), _abi._dptr(bb), _abi._dptr(cb)))
     return (cb[0::2] + 1j * cb[1::2]).reshape(M, N)
+
+
+def svd_trunc(ctx, T, D, cutoff=1e-10, s_left=True):
+    """Truncated SVD on the device: returns (L, R) with T ~ L @ R."""
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.complex128))
+    M, N = T.shape
+    ns = min(M, N)
+    tb = np.empty(2 * T.size); tb[0::2] = T.real.reshape(-1); tb[1::2] = T.imag.reshape(-1)
+    Lb = np.zeros(2 * M * ns)
+    Rb = np.zeros(2 * ns * N)
+    k = C.c_int32()
+    check(lib.ftd_svd_trunc(ctx.h, M, N, _abi._dptr(tb), int(D), float(cutoff), int(bool(s_left)),
+                            _abi._dptr(Lb), _abi._dptr(Rb), C.byref(k)))
+    k = k.value
+    L = (Lb[0::2] + 1j * Lb[1::2])[: M * k].reshape(M, k)
+    R = (Rb[0::2] + 1j * Rb[1::2])[: k * N].reshape(k, N)
+    return L, R
 
 
 def heff_apply(ctx, H, psi, site, x, n_repeat=1):

@@ -62,19 +62,6 @@ static std::vector<double> max_bond(const Mps* psi) {
     return out;
 }
 
-static Mps* taylor_growth(Ctx* ctx, const Mpo* H, const Mps* psi, double dtau, int D,
-                          double cutoff) {
-    Mps* phi = mps_clone(psi);
-    for (int k = 4; k >= 1; --k) {
-        Mps* Hphi = mpo_apply(ctx, H, phi);
-        mps_free(phi);
-        Mps* X = mps_add(ctx, psi, Hphi, cplx(-dtau / k, 0.0));
-        mps_free(Hphi);
-        phi = compress(ctx, X, D, cutoff, true);
-    }
-    return phi;
-}
-
 }  // namespace ftd
 
 using namespace ftd;
@@ -334,6 +321,13 @@ ftd_status ftd_mps_from_host(ftd_ctx* ctx, int32_t n_sites, const int32_t* dims,
     });
 }
 
+ftd_status ftd_mps_set_precision(ftd_mps* psi, ftd_precision prec) {
+    return guarded([&] {
+        FTD_CHECK(psi, FTD_EINVAL, "null argument");
+        psi->m->prec = to_prec(prec);
+    });
+}
+
 ftd_status ftd_mps_norm(ftd_ctx* ctx, const ftd_mps* psi, double* out) {
     return guarded([&] {
         FTD_CHECK(ctx && psi && out, FTD_EINVAL, "null argument");
@@ -457,6 +451,16 @@ ftd_status ftd_apply_compress(ftd_ctx* ctx, const ftd_mpo* O, const ftd_mps* psi
     });
 }
 
+ftd_status ftd_pc_stage(ftd_ctx* ctx, const ftd_mps* psi, const ftd_mpo* O, const ftd_mps* phi,
+                        const double* c, int32_t D, double cutoff, ftd_mps** out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && psi && O && phi && c && out, FTD_EINVAL, "null argument");
+        FTD_CHECK(D >= 1, FTD_EINVAL, "D must be >= 1");
+        Mps* r = pc_stage(&ctx->c, psi->m, O->m, phi->m, cplx(c[0], c[1]), D, cutoff);
+        *out = new ftd_mps{r};
+    });
+}
+
 ftd_status ftd_overlap(ftd_ctx* ctx, const ftd_mps* bra, const ftd_mpo* O, const ftd_mps* ket,
                        double* out) {
     return guarded([&] {
@@ -528,6 +532,39 @@ ftd_status ftd_heff_apply(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, in
     return guarded([&] {
         FTD_CHECK(ctx && H && psi && x && y, FTD_EINVAL, "null argument");
         heff_apply_host(&ctx->c, H->m, psi->m, site, x, y, n_repeat);
+    });
+}
+
+ftd_status ftd_svd_trunc(ftd_ctx* ctx, int32_t M, int32_t N, const double* T, int32_t D,
+                         double cutoff, int32_t s_left, double* L, double* R, int32_t* kout) {
+    return guarded([&] {
+        FTD_CHECK(ctx && T && L && R && kout, FTD_EINVAL, "null argument");
+        FTD_CHECK(M >= 1 && N >= 1 && D >= 1, FTD_EINVAL, "bad sizes");
+        Ctx* c = &ctx->c;
+        const int64_t n = (int64_t)M * N;
+        double* dT = static_cast<double*>(dev_alloc(c, sizeof(double) * 2 * n));
+        std::vector<double> t(2 * n);
+        for (int64_t i = 0; i < n; ++i) {
+            t[i] = T[2 * i];
+            t[i + n] = T[2 * i + 1];
+        }
+        FTD_HIP(hipMemcpy(dT, t.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice));
+        TruncOut o = svd_trunc(c, dT, M, N, D, cutoff, s_left != 0);
+        const int k = o.k;
+        auto down = [&](const double* d, int64_t cnt, double* h) {
+            std::vector<double> b(2 * cnt);
+            FTD_HIP(hipMemcpy(b.data(), d, sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < cnt; ++i) {
+                h[2 * i] = b[i];
+                h[2 * i + 1] = b[i + cnt];
+            }
+        };
+        down(o.Lq, (int64_t)M * k, L);
+        down(o.Rq, (int64_t)k * N, R);
+        dev_free(c, dT);
+        dev_free(c, o.Lq);
+        dev_free(c, o.Rq);
+        *kout = k;
     });
 }
 

@@ -105,6 +105,7 @@ struct MixEnt {
 };
 struct MixParams {
     int Da, d, Db;
+    int64_t ldIn, ldOut;   // row strides of the b index (0 = Db)
     int64_t planeIn, planeOut;
     int64_t opStride;   // elements per op (re plane then im plane, d*d each)
     int accumulate;
@@ -135,7 +136,7 @@ void k_lincomb(Ctx* ctx, const double* V, int64_t vstride, int k, const double* 
                const double* scale_dev, double* y, int64_t n, int64_t plane);
 // embed src[Da][dd][Db] into dst[DA][dd][DB] at (a0, b0), times (re, im)
 void k_embed(Ctx* ctx, const double* src, int Da, int dd, int Db, double* dst, int DA, int DB,
-             int a0, int b0, double re, double im);
+             int a0, int b0, double re, double im, int accumulate = 0);
 // exact MPO x MPS site product
 struct ApplyEnt {
     int cl, cr, op;
@@ -168,9 +169,12 @@ void k_set_alpha(Ctx* ctx, KrylovDev kd, int k);
 void qr_chol(Ctx* ctx, double* M, int64_t m, int64_t n, double* R);
 // LQ of a full-row-rank M (n x m row-major): M = L Q, Q overwrites M, L n x n.
 void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L);
-// Householder QR for any rank (m x n row-major, m >= 1): Q (m x r) and R
-// (r x n), r = min(m, n), diag(R) real >= 0.
-void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, double* R);
+// Householder QR for any rank of an m x n matrix A: Q (m x r, row-major, not
+// formed when Q is null) and R (r x n, row-major), r = min(m, n), diag(R)
+// real >= 0.  A = M (row-major m x n), or A = M^H for a row-major n x m M
+// when adjoint is set.
+void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, double* R,
+                    bool adjoint = false);
 // Thin SVD of X (m x n, row-major, m >= n) by one-sided Jacobi:
 // X = U S V^H, U m x n (columns scaled), S[n] sorted descending, V n x n.
 void svd_jacobi(Ctx* ctx, const double* X, int64_t m, int64_t n, double* U, double* S,
@@ -260,6 +264,15 @@ Mps* identity_mps(Ctx* ctx, const Mpo* H);
 void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax);
 Mps* apply_compress(Ctx* ctx, const Mpo* O, const Mps* psi, int D, double cutoff);
 Mps* compress(Ctx* ctx, Mps* X, int D, double cutoff, bool consume);
+struct TruncOut {
+    int k;
+    double* Lq;
+    double* Rq;
+};
+TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, double cutoff,
+                   bool s_left);
+Mps* taylor_growth(Ctx* ctx, const Mpo* H, const Mps* psi, double dtau, int D, double cutoff);
+Mps* pc_stage(Ctx* ctx, const Mps* psi, const Mpo* O, const Mps* phi, cplx c, int D, double cutoff);
 Mps* mps_add(Ctx* ctx, const Mps* a, const Mps* b, cplx c);
 Mps* mpo_apply(Ctx* ctx, const Mpo* O, const Mps* psi);
 double mps_normalize(Ctx* ctx, Mps* psi);

@@ -808,154 +808,469 @@ static int truncation_rank(const std::vector<double>& s, int D, double cutoff) {
     return k;
 }
 
-// Left QR sweep (Householder) then right-to-left SVD truncation (Jacobi).
-Mps* compress(Ctx* ctx, Mps* X, int D, double cutoff, bool consume) {
-    Mps* Y = consume ? X : mps_clone(X);
-    const int L = Y->L;
-    for (int i = 0; i < L - 1; ++i) {
-        const int d = Y->d[i];
-        const int64_t m = (int64_t)Y->Dl[i] * d * d, nc = Y->Dr[i];
-        const int r = (int)std::min<int64_t>(m, nc);
-        double* Q = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * r));
-        ctx->ws_tmp2.ensure(ctx, sizeof(double) * 2 * (size_t)r * nc);
-        double* R = ctx->ws_tmp2.as<double>();
-        qr_householder(ctx, Y->A[i], m, nc, Q, R);
-        set_site(ctx, Y, i, Y->Dl[i], r, Q);
-        // A_{i+1} <- R A_{i+1}
-        const int64_t nn = Y->size(i + 1);
-        const int64_t cols = nn / nc;
-        double* B = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * r * cols));
-        GemmParams p{};
-        p.M = r; p.N = (int)cols; p.K = (int)nc;
-        p.sAm = nc; p.sAk = 1; p.planeA = (int64_t)r * nc; p.a_kcontig = 1;
-        p.sBk = cols; p.sBn = 1; p.planeB = nn; p.b_kcontig = 0;
-        p.sCm = cols; p.sCn = 1; p.planeC = (int64_t)r * cols;
-        p.nprob = 1; p.prob[0].t1 = 1;
-        gemm(ctx, Prec::F64, true, R, Y->A[i + 1], B, p, TAG_NONE);
-        set_site(ctx, Y, i + 1, r, Y->Dr[i + 1], B);
-    }
-    for (int i = L - 1; i >= 1; --i) {
-        const int d = Y->d[i];
-        const int64_t rows = Y->Dl[i], c = (int64_t)d * d * Y->Dr[i];
-        const int64_t ns = std::min(rows, c);
-        // left vectors times S (rows x k, col-major) and new A_i (k x c, row-major)
-        ctx->ws_svd1.ensure(ctx, sizeof(double) * 2 * (size_t)(rows * c + ns * ns + rows * ns + ns));
-        double* Ub = ctx->ws_svd1.as<double>();
-        double* Vb = Ub + 2 * rows * c;
-        double* Sd = Vb + 2 * ns * ns;
-        std::vector<double> S(ns);
-        std::vector<int> perm(ns);
-        int k = 0;
-        double* LS = nullptr;
-        double* Anew = nullptr;
-        auto finish_perm = [&]() {
-            FTD_HIP(hipMemcpyAsync(S.data(), Sd, sizeof(double) * ns, hipMemcpyDeviceToHost, ctx->stream));
-            FTD_HIP(hipStreamSynchronize(ctx->stream));
-            std::iota(perm.begin(), perm.end(), 0);
-            std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return S[a] > S[b]; });
-            std::vector<double> ss(ns);
-            for (int j = 0; j < ns; ++j) ss[j] = S[perm[j]];
-            k = truncation_rank(ss, D, cutoff);
-        };
-        ctx->ws_perm.ensure(ctx, sizeof(int) * ns + sizeof(double) * 2 * ns + 64);
-        int* dperm = ctx->ws_perm.as<int>();
-        double* dsc = reinterpret_cast<double*>(static_cast<char*>(ctx->ws_perm.p) + ((sizeof(int) * ns + 15) / 16) * 16);
-        auto upload = [&](const std::vector<double>& sc) {
-            std::vector<int> pk(perm.begin(), perm.begin() + k);
-            FTD_HIP(hipMemcpyAsync(dperm, pk.data(), sizeof(int) * k, hipMemcpyHostToDevice, ctx->stream));
-            FTD_HIP(hipMemcpyAsync(dsc, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
-            FTD_HIP(hipStreamSynchronize(ctx->stream));
-        };
-        if (c <= rows) {
-            // C = U S V^H directly: U (rows x c, scaled), V (c x c)
-            svd_jacobi(ctx, Y->A[i], rows, c, Ub, Sd, Vb);
-            finish_perm();
-            upload(std::vector<double>(k, 1.0));
-            LS = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * k));
-            gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(Ub, rows, rows * c, dperm, nullptr, k, 0, LS, rows * k);
-            Anew = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * c * k));
-            gather_cols_kernel<<<gr(c * k), 256, 0, ctx->stream>>>(Vb, c, c * c, dperm, nullptr, k, 1, Anew, c * k);
-        } else {
-            // work on C^H (c x rows)
-            ctx->ws_tmp3.ensure(ctx, sizeof(double) * 2 * (size_t)c * rows);
-            double* CH = ctx->ws_tmp3.as<double>();
-            k_transpose(ctx, Y->A[i], rows, c, rows * c, CH, rows * c, 1);
-            if (c >= 2 * rows && rows > 1) {
-                double* Q = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * c * rows));
-                double* R = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * rows));
-                qr_householder(ctx, CH, c, rows, Q, R);
-                // R = U' S V'^H
-                svd_jacobi(ctx, R, rows, rows, Ub, Sd, Vb);
-                finish_perm();
-                std::vector<double> sc(k), inv(k);
-                for (int j = 0; j < k; ++j) {
-                    sc[j] = S[perm[j]];
-                    inv[j] = S[perm[j]] > 0.0 ? 1.0 / S[perm[j]] : 0.0;
-                }
-                upload(sc);
-                LS = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * k));
-                gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(Vb, rows, rows * rows, dperm, dsc, k, 0, LS, rows * k);
-                upload(inv);
-                double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * k));
-                gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(Ub, rows, rows * rows, dperm, dsc, k, 0, G, rows * k);
-                // A_new (k x c) = conj(Q G)^T
-                Anew = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * c * k));
-                GemmParams p{};
-                p.M = (int)c; p.N = k; p.K = (int)rows;
-                p.sAm = rows; p.sAk = 1; p.planeA = c * rows; p.conjA = 1; p.a_kcontig = 1;
-                p.sBk = 1; p.sBn = rows; p.planeB = rows * k; p.conjB = 1; p.b_kcontig = 1;
-                p.sCm = 1; p.sCn = c; p.planeC = c * k;
-                p.nprob = 1; p.prob[0].t1 = 1;
-                gemm(ctx, Prec::F64, true, Q, G, Anew, p, TAG_NONE);
-                FTD_HIP(hipStreamSynchronize(ctx->stream));
-                dev_free(ctx, Q);
-                dev_free(ctx, R);
-                dev_free(ctx, G);
-            } else {
-                svd_jacobi(ctx, CH, c, rows, Ub, Sd, Vb);
-                finish_perm();
-                std::vector<double> sc(k), inv(k);
-                for (int j = 0; j < k; ++j) {
-                    sc[j] = S[perm[j]];
-                    inv[j] = S[perm[j]] > 0.0 ? 1.0 / S[perm[j]] : 0.0;
-                }
-                upload(sc);
-                LS = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rows * k));
-                gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(Vb, rows, rows * rows, dperm, dsc, k, 0, LS, rows * k);
-                upload(inv);
-                Anew = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * c * k));
-                gather_cols_kernel<<<gr(c * k), 256, 0, ctx->stream>>>(Ub, c, c * rows, dperm, dsc, k, 1, Anew, c * k);
-            }
-        }
-        FTD_HIP(hipGetLastError());
-        set_site(ctx, Y, i, k, Y->Dr[i], Anew);
-        // A_{i-1} <- A_{i-1} LS
-        const int64_t nn = Y->size(i - 1);
-        const int64_t r2 = nn / rows;
-        double* B = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * r2 * k));
-        GemmParams p{};
-        p.M = (int)r2; p.N = k; p.K = (int)rows;
-        p.sAm = rows; p.sAk = 1; p.planeA = nn; p.a_kcontig = 1;
-        p.sBk = 1; p.sBn = rows; p.planeB = rows * k; p.b_kcontig = 1;
-        p.sCm = k; p.sCn = 1; p.planeC = r2 * k;
-        p.nprob = 1; p.prob[0].t1 = 1;
-        gemm(ctx, Prec::F64, true, Y->A[i - 1], LS, B, p, TAG_NONE);
+// Truncated SVD of T (m x n, row-major, split planes m*n):
+//   T ~ Lq diag(S) Rq,  Lq m x k (orthonormal columns), Rq k x n (orthonormal
+//   rows), k from truncation_rank.  S is multiplied into Lq (s_left) or Rq.
+// Tall blocks (m >= 2n) are reduced by Householder QR first; the small factor
+// is diagonalised by one-sided Jacobi.  Returns newly allocated buffers.
+TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, double cutoff,
+                          bool s_left) {
+    const int64_t ns = std::min(m, n);
+    const int64_t big = std::max(m, n);
+    ctx->ws_svd1.ensure(ctx, sizeof(double) * 2 * (size_t)(big * ns + ns * ns + ns));
+    double* Ub = ctx->ws_svd1.as<double>();
+    double* Vb = Ub + 2 * big * ns;
+    double* Sd = Vb + 2 * ns * ns;
+    std::vector<double> S(ns);
+    std::vector<int> perm(ns);
+    int k = 0;
+    auto finish = [&]() {
+        FTD_HIP(hipMemcpyAsync(S.data(), Sd, sizeof(double) * ns, hipMemcpyDeviceToHost, ctx->stream));
         FTD_HIP(hipStreamSynchronize(ctx->stream));
-        dev_free(ctx, LS);
-        set_site(ctx, Y, i - 1, Y->Dl[i - 1], k, B);
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return S[x] > S[y]; });
+        std::vector<double> ss(ns);
+        for (int j = 0; j < ns; ++j) ss[j] = S[perm[j]];
+        k = truncation_rank(ss, D, cutoff);
+    };
+    ctx->ws_perm.ensure(ctx, 64 + (sizeof(int) + 3 * sizeof(double)) * (size_t)ns);
+    int* dperm = ctx->ws_perm.as<int>();
+    double* dS = reinterpret_cast<double*>(static_cast<char*>(ctx->ws_perm.p) +
+                                           ((sizeof(int) * ns + 63) / 64) * 64);
+    double* dInv = dS + ns;
+    auto upload = [&]() {
+        std::vector<double> sv(k), iv(k);
+        for (int j = 0; j < k; ++j) {
+            sv[j] = S[perm[j]];
+            iv[j] = sv[j] > 0.0 ? 1.0 / sv[j] : 0.0;
+        }
+        FTD_HIP(hipMemcpyAsync(dperm, perm.data(), sizeof(int) * k, hipMemcpyHostToDevice, ctx->stream));
+        FTD_HIP(hipMemcpyAsync(dS, sv.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+        FTD_HIP(hipMemcpyAsync(dInv, iv.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+    };
+    auto gather = [&](const double* src, int64_t rows, int64_t splane, const double* sc, int conj,
+                      double* dst) {
+        gather_cols_kernel<<<gr(rows * k), 256, 0, ctx->stream>>>(src, rows, splane, dperm, sc, k, conj,
+                                                                  dst, rows * k);
+        FTD_HIP(hipGetLastError());
+    };
+    TruncOut o{0, nullptr, nullptr};
+    if (m >= n) {
+        if (m >= 2 * n && n > 1) {
+            double* Q = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * n));
+            double* R = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * n));
+            qr_householder(ctx, T, m, n, Q, R);
+            svd_jacobi(ctx, R, n, n, Ub, Sd, Vb);       // R = U' S V'^H, Ub = U' S
+            finish();
+            upload();
+            double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * k));
+            gather(Ub, n, n * n, s_left ? nullptr : dInv, 0, G);
+            o.Lq = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * k));
+            GemmParams p{};
+            p.M = (int)m; p.N = k; p.K = (int)n;
+            p.sAm = n; p.sAk = 1; p.planeA = m * n; p.a_kcontig = 1;
+            p.sBk = 1; p.sBn = n; p.planeB = n * k; p.b_kcontig = 1;
+            p.sCm = k; p.sCn = 1; p.planeC = m * k;
+            p.nprob = 1; p.prob[0].t1 = 1;
+            gemm(ctx, Prec::F64, true, Q, G, o.Lq, p, TAG_NONE);
+            o.Rq = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * k));
+            gather(Vb, n, n * n, s_left ? nullptr : dS, 1, o.Rq);
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+            dev_free(ctx, Q);
+            dev_free(ctx, R);
+            dev_free(ctx, G);
+        } else {
+            svd_jacobi(ctx, T, m, n, Ub, Sd, Vb);       // T V = U S, Ub = U S (m x n)
+            finish();
+            upload();
+            double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * k));
+            gather(Ub, m, m * n, s_left ? nullptr : dInv, 0, G);
+            o.Lq = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * k));
+            k_transpose(ctx, G, k, m, m * k, o.Lq, m * k, 0);
+            o.Rq = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * k));
+            gather(Vb, n, n * n, s_left ? nullptr : dS, 1, o.Rq);
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+            dev_free(ctx, G);
+        }
+    } else {
+        ctx->ws_tmp3.ensure(ctx, sizeof(double) * 2 * (size_t)m * n);
+        double* TH = ctx->ws_tmp3.as<double>();
+        k_transpose(ctx, T, m, n, m * n, TH, m * n, 1);   // n x m
+        svd_jacobi(ctx, TH, n, m, Ub, Sd, Vb);           // T^H = U S V^H, Ub = U S (n x m)
+        finish();
+        upload();
+        double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * k));
+        gather(Vb, m, m * m, s_left ? dS : nullptr, 0, G);
+        o.Lq = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * k));
+        k_transpose(ctx, G, k, m, m * k, o.Lq, m * k, 0);
+        o.Rq = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * k));
+        gather(Ub, n, n * m, s_left ? dInv : nullptr, 1, o.Rq);
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+        dev_free(ctx, G);
     }
+    o.k = k;
+    return o;
+}
+
+// SVD compression of sum_t c_t O_t |psi_t> (O_t an MPO or the identity)
+// without storing the exact sum X, whose bonds are as wide as the MPO bond
+// times the state bond:
+//   1. right to left, the exact remainder of X beyond each bond is factored
+//      as R_b Q_{>b} with Q right-orthonormal; only the small factor R_b
+//      (bond width x rank) is kept: R_b is the L factor of X_{b+1} R_{b+1};
+//   2. left to right, the partial product T_i = C X_i is multiplied by R_i,
+//      which makes it the true centre matrix across bond i, and truncated by
+//      SVD (at most D singular values with s/s_max > cutoff, whole
+//      multiplets); the kept left vectors become the site tensor and
+//      C = U^H T_i is carried on;
+//   3. an LQ sweep returns the state to right-canonical form.
+// The result depends only on the state X, not on the MPO's channel basis.
+struct ZipTerm {
+    cplx c;
+    const Mpo* O;   // nullptr: identity
+    const Mps* psi;
+};
+
+namespace {
+// bond b = right of site b; b = L-1 is the boundary where the terms add up
+struct BondLayout {
+    int64_t width;
+    std::vector<int64_t> off;   // per term
+};
+BondLayout bond_layout(const std::vector<ZipTerm>& terms, int b, int L) {
+    BondLayout bl;
+    bl.width = 0;
+    for (auto& t : terms) {
+        bl.off.push_back(bl.width);
+        if (b >= L - 1)
+            bl.width += 1;
+        else
+            bl.width += (t.O ? (int64_t)t.O->s[b].wr : 1) * t.psi->Dr[b];
+    }
+    return bl;
+}
+}  // namespace
+
+// M = X_s R_in as a (width of bond s-1) x (d^2 r) row-major matrix.
+static void form_M(Ctx* ctx, const std::vector<ZipTerm>& terms, int s, const double* Rin,
+                   int64_t rin_rows, int r, const BondLayout& left, const BondLayout& right,
+                   double* M) {
+    const int d = terms[0].psi->d[s];
+    const int64_t rowlen = (int64_t)d * d * r;
+    const int64_t nM = left.width * rowlen;
+    k_zero(ctx, M, sizeof(double) * 2 * nM);
+    const int64_t rplane = rin_rows * r;
+    for (size_t t = 0; t < terms.size(); ++t) {
+        const Mps* ps = terms[t].psi;
+        const int Dl = ps->Dl[s], Dr = ps->Dr[s];
+        const int64_t npsi = ps->size(s);
+        GemmParams p{};
+        p.M = Dl * d * d; p.N = r; p.K = Dr;
+        p.sAm = Dr; p.sAk = 1; p.planeA = npsi; p.a_kcontig = 1;
+        p.sBk = r; p.sBn = 1; p.planeB = rplane; p.b_kcontig = 0;
+        if (!terms[t].O) {
+            p.sCm = r; p.sCn = 1; p.planeC = nM;
+            p.nprob = 1; p.prob[0].t1 = 1;
+            p.prob[0].offC = left.off[t] * rowlen;
+            p.term[0].offB = right.off[t] * r;
+            gemm(ctx, Prec::F64, true, ps->A[s], Rin, M, p, TAG_NONE);
+            continue;
+        }
+        const MpoSite& W = terms[t].O->s[s];
+        const int wl = W.wl, wr = W.wr;
+        const int64_t nY = (int64_t)Dl * d * d * r;
+        ctx->ws_U.ensure(ctx, sizeof(double) * 2 * nY * wr);
+        double* Y = ctx->ws_U.as<double>();
+        p.sCm = r; p.sCn = 1; p.planeC = nY;
+        for (int c0 = 0; c0 < wr; c0 += kMaxProbs) {
+            const int c1 = std::min(wr, c0 + kMaxProbs);
+            p.nprob = c1 - c0;
+            for (int c = c0; c < c1; ++c) {
+                const int j = c - c0;
+                p.prob[j].offC = (int64_t)c * 2 * nY;
+                p.prob[j].t0 = j;
+                p.prob[j].t1 = j + 1;
+                p.term[j].offA = 0;
+                p.term[j].offB = (right.off[t] + (int64_t)c * Dr) * r;
+            }
+            gemm(ctx, Prec::F64, true, ps->A[s], Rin, Y, p, TAG_NONE);
+        }
+        // M[(cl, a), p', q, j] = sum_cr sum_p W[cl, cr][p', p] Y_cr[a, p, q, j]
+        std::vector<std::vector<std::pair<int, int>>> col(wl);
+        for (size_t e = 0; e < W.ents.size(); ++e) col[W.ents[e].cl].push_back({W.ents[e].cr, (int)e});
+        MixParams mp{};
+        mp.Da = Dl; mp.d = d; mp.Db = r;
+        mp.planeIn = nY; mp.planeOut = nM;
+        mp.opStride = 2 * (int64_t)d * d;
+        int ne = 0;
+        for (int cl = 0; cl < wl; ++cl) {
+            if (col[cl].empty()) continue;
+            if (mp.njobs == kMaxMixJobs || ne + (int)col[cl].size() > kMaxMixEnts) {
+                chanmix(ctx, Prec::F64, true, Y, W.ops64, M, mp);
+                mp.njobs = 0;
+                ne = 0;
+            }
+            mp.job[mp.njobs] = {(left.off[t] + (int64_t)cl * Dl) * rowlen, ne, ne + (int)col[cl].size()};
+            for (auto& pr : col[cl]) mp.ent[ne++] = {(int64_t)pr.first * 2 * nY, pr.second};
+            mp.njobs++;
+        }
+        if (mp.njobs) chanmix(ctx, Prec::F64, true, Y, W.ops64, M, mp);
+    }
+}
+
+// T = C X_i: (Dp d^2) x (width of bond i), or at the last site the sum over
+// terms as a single column.
+static double* form_T(Ctx* ctx, const std::vector<ZipTerm>& terms, int i, const double* C,
+                      int64_t ldC, int Dp, const BondLayout& left, const BondLayout& right,
+                      bool last, int64_t& ncols) {
+    const int d = terms[0].psi->d[i];
+    ncols = last ? 1 : right.width;
+    const int64_t m = (int64_t)Dp * d * d;
+    const int64_t Tn = m * ncols;
+    double* T = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * Tn));
+    k_zero(ctx, T, sizeof(double) * 2 * Tn);
+    for (size_t t = 0; t < terms.size(); ++t) {
+        const Mps* ps = terms[t].psi;
+        const int Dlt = ps->Dl[i], Drt = ps->Dr[i];
+        const int64_t nX = (int64_t)Dp * d * d * Drt;
+        const int64_t npsi = ps->size(i);
+        const int64_t toff = last ? 0 : right.off[t];
+        if (!terms[t].O) {
+            ctx->ws_U.ensure(ctx, sizeof(double) * 2 * nX);
+            double* X = ctx->ws_U.as<double>();
+            GemmParams p{};
+            p.M = Dp; p.N = d * d * Drt; p.K = Dlt;
+            p.sAm = ldC; p.sAk = 1; p.planeA = (int64_t)Dp * ldC; p.a_kcontig = 1;
+            p.sBk = (int64_t)d * d * Drt; p.sBn = 1; p.planeB = npsi; p.b_kcontig = 0;
+            p.sCm = (int64_t)d * d * Drt; p.sCn = 1; p.planeC = nX;
+            p.nprob = 1; p.prob[0].t1 = 1;
+            p.term[0].offA = left.off[t];
+            gemm(ctx, Prec::F64, true, C, ps->A[i], X, p, TAG_NONE);
+            k_embed(ctx, X, Dp, d * d, Drt, T, Dp, (int)ncols, 0, (int)toff, 1.0, 0.0, 1);
+            continue;
+        }
+        const MpoSite& W = terms[t].O->s[i];
+        const int wl = W.wl, wr = W.wr;
+        ctx->ws_U.ensure(ctx, sizeof(double) * 2 * nX * wl);
+        double* X = ctx->ws_U.as<double>();
+        for (int c0 = 0; c0 < wl; c0 += kMaxProbs) {
+            const int c1 = std::min(wl, c0 + kMaxProbs);
+            GemmParams p{};
+            p.M = Dp; p.N = d * d * Drt; p.K = Dlt;
+            p.sAm = ldC; p.sAk = 1; p.planeA = (int64_t)Dp * ldC; p.a_kcontig = 1;
+            p.sBk = (int64_t)d * d * Drt; p.sBn = 1; p.planeB = npsi; p.b_kcontig = 0;
+            p.sCm = (int64_t)d * d * Drt; p.sCn = 1; p.planeC = nX;
+            p.nprob = c1 - c0;
+            for (int c = c0; c < c1; ++c) {
+                const int j = c - c0;
+                p.prob[j].offC = (int64_t)c * 2 * nX;
+                p.prob[j].t0 = j;
+                p.prob[j].t1 = j + 1;
+                p.term[j].offA = left.off[t] + (int64_t)c * Dlt;
+                p.term[j].offB = 0;
+            }
+            gemm(ctx, Prec::F64, true, C, ps->A[i], X, p, TAG_NONE);
+        }
+        std::vector<std::vector<std::pair<int, int>>> col(wr);
+        for (size_t e = 0; e < W.ents.size(); ++e) col[W.ents[e].cr].push_back({W.ents[e].cl, (int)e});
+        MixParams mp{};
+        mp.Da = Dp; mp.d = d; mp.Db = Drt;
+        mp.ldIn = Drt; mp.ldOut = ncols;
+        mp.planeIn = nX; mp.planeOut = Tn;
+        mp.opStride = 2 * (int64_t)d * d;
+        mp.accumulate = 1;
+        int ne = 0;
+        for (int cr = 0; cr < wr; ++cr) {
+            if (col[cr].empty()) continue;
+            if (mp.njobs == kMaxMixJobs || ne + (int)col[cr].size() > kMaxMixEnts) {
+                chanmix(ctx, Prec::F64, true, X, W.ops64, T, mp);
+                mp.njobs = 0;
+                ne = 0;
+            }
+            mp.job[mp.njobs] = {toff + (int64_t)cr * Drt, ne, ne + (int)col[cr].size()};
+            for (auto& pr : col[cr]) mp.ent[ne++] = {(int64_t)pr.first * 2 * nX, pr.second};
+            mp.njobs++;
+        }
+        if (mp.njobs) chanmix(ctx, Prec::F64, true, X, W.ops64, T, mp);
+    }
+    return T;
+}
+
+// LQ sweep from the right (no truncation): right-canonical, norm on site 0.
+static void lq_sweep(Ctx* ctx, Mps* Y) {
+    for (int i = Y->L - 1; i >= 1; --i) {
+        const int Da = Y->Dl[i], d = Y->d[i], Db = Y->Dr[i];
+        ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Da * Da);
+        double* Lm = ctx->ws_tmp1.as<double>();
+        lq_chol(ctx, Y->A[i], Da, (int64_t)d * d * Db, Lm);
+        absorb_left(ctx, Y, i, Lm);
+    }
+}
+
+static Mps* compress_terms(Ctx* ctx, const std::vector<ZipTerm>& terms, int D, double cutoff) {
+    FTD_CHECK(!terms.empty(), FTD_EINVAL, "compress: no terms");
+    const int L = terms[0].psi->L;
+    for (auto& t : terms) {
+        FTD_CHECK(t.psi->L == L && (!t.O || t.O->L == L), FTD_EINVAL, "compress: lengths differ");
+        FTD_CHECK(std::abs(t.psi->log_norm - terms[0].psi->log_norm) <=
+                      1e-15 * std::max(1.0, std::abs(terms[0].psi->log_norm)),
+                  FTD_EINVAL, "compress: terms carry different norms");
+    }
+    const int nt = (int)terms.size();
+    std::vector<BondLayout> bonds(L);
+    for (int b = 0; b < L; ++b) bonds[b] = bond_layout(terms, b, L);
+    BondLayout left0;
+    left0.width = nt;
+    for (int t = 0; t < nt; ++t) left0.off.push_back(t);
+    // 1. metric factors R_b (bond width x rank), right to left
+    std::vector<double*> Rf(L, nullptr);
+    std::vector<int> rk(L, 0);
+    Mps* Y = nullptr;
+    double* C = nullptr;
+    try {
+        {
+            std::vector<double> ones(2 * nt, 0.0);
+            for (int t = 0; t < nt; ++t) ones[t] = 1.0;
+            Rf[L - 1] = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * nt));
+            FTD_HIP(hipMemcpyAsync(Rf[L - 1], ones.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice, ctx->stream));
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+            rk[L - 1] = 1;
+        }
+        for (int s = L - 1; s >= 1; --s) {
+            const BondLayout& lb = bonds[s - 1];
+            const BondLayout& rb = bonds[s];
+            const int d = terms[0].psi->d[s];
+            const int r = rk[s];
+            const int64_t cols = (int64_t)d * d * r;
+            ctx->ws_tmp2.ensure(ctx, sizeof(double) * 2 * (size_t)(lb.width * cols));
+            double* M = ctx->ws_tmp2.as<double>();
+            form_M(ctx, terms, s, Rf[s], rb.width, r, lb, rb, M);
+            // M = L Q: QR of M^H (cols x width), L = R^H
+            const int64_t rr = std::min<int64_t>(cols, lb.width);
+            double* Rp = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * rr * lb.width));
+            qr_householder(ctx, M, cols, lb.width, nullptr, Rp, true);
+            Rf[s - 1] = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * lb.width * rr));
+            k_transpose(ctx, Rp, rr, lb.width, rr * lb.width, Rf[s - 1], rr * lb.width, 1);
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+            dev_free(ctx, Rp);
+            rk[s - 1] = (int)rr;
+        }
+        // 2. left-to-right truncation of the true centre matrices
+        Y = new Mps();
+        Y->ctx = ctx;
+        Y->L = L;
+        Y->d = terms[0].psi->d;
+        Y->Dl.assign(L, 1);
+        Y->Dr.assign(L, 1);
+        Y->A.assign(L, nullptr);
+        Y->prec = terms[0].psi->prec;
+        Y->log_norm = terms[0].psi->log_norm;
+        {
+            std::vector<double> h(2 * nt);
+            for (int t = 0; t < nt; ++t) {
+                h[t] = terms[t].c.real();
+                h[nt + t] = terms[t].c.imag();
+            }
+            C = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * nt));
+            FTD_HIP(hipMemcpyAsync(C, h.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice, ctx->stream));
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+        }
+        int64_t ldC = nt;
+        int Dp = 1;
+        for (int i = 0; i < L; ++i) {
+            const bool last = (i == L - 1);
+            const BondLayout& lb = (i == 0) ? left0 : bonds[i - 1];
+            int64_t ncols = 0;
+            double* T = form_T(ctx, terms, i, C, ldC, Dp, lb, bonds[i], last, ncols);
+            const int d = Y->d[i];
+            const int64_t m = (int64_t)Dp * d * d;
+            if (last) {
+                FTD_HIP(hipStreamSynchronize(ctx->stream));
+                dev_free(ctx, C);
+                C = nullptr;
+                Y->A[i] = T;
+                Y->Dl[i] = Dp;
+                break;
+            }
+            const int r = rk[i];
+            double* P = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * r));
+            {
+                GemmParams p{};
+                p.M = (int)m; p.N = r; p.K = (int)ncols;
+                p.sAm = ncols; p.sAk = 1; p.planeA = m * ncols; p.a_kcontig = 1;
+                p.sBk = r; p.sBn = 1; p.planeB = ncols * r; p.b_kcontig = 0;
+                p.sCm = r; p.sCn = 1; p.planeC = m * r;
+                p.nprob = 1; p.prob[0].t1 = 1;
+                gemm(ctx, Prec::F64, true, T, Rf[i], P, p, TAG_NONE);
+            }
+            TruncOut tr = svd_trunc(ctx, P, m, r, D, cutoff, false);
+            const int k = tr.k;
+            double* Cn = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * (int64_t)k * ncols));
+            {
+                GemmParams p{};
+                p.M = k; p.N = (int)ncols; p.K = (int)m;
+                p.sAm = 1; p.sAk = k; p.planeA = m * k; p.conjA = 1; p.a_kcontig = 0;
+                p.sBk = ncols; p.sBn = 1; p.planeB = m * ncols; p.b_kcontig = 0;
+                p.sCm = ncols; p.sCn = 1; p.planeC = (int64_t)k * ncols;
+                p.nprob = 1; p.prob[0].t1 = 1;
+                gemm(ctx, Prec::F64, true, tr.Lq, T, Cn, p, TAG_NONE);
+            }
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+            dev_free(ctx, T);
+            dev_free(ctx, P);
+            dev_free(ctx, tr.Rq);
+            dev_free(ctx, C);
+            C = Cn;
+            ldC = ncols;
+            Y->A[i] = tr.Lq;
+            Y->Dl[i] = Dp;
+            Y->Dr[i] = k;
+            Dp = k;
+        }
+    } catch (...) {
+        for (auto p : Rf) dev_free(ctx, p);
+        dev_free(ctx, C);
+        mps_free(Y);
+        throw;
+    }
+    for (auto p : Rf) dev_free(ctx, p);
+    // 3. back to right-canonical form
+    lq_sweep(ctx, Y);
     FTD_HIP(hipStreamSynchronize(ctx->stream));
     return Y;
 }
 
+Mps* compress(Ctx* ctx, Mps* X, int D, double cutoff, bool consume) {
+    Mps* Y = compress_terms(ctx, {ZipTerm{cplx(1.0, 0.0), nullptr, X}}, D, cutoff);
+    if (consume) mps_free(X);
+    return Y;
+}
+
 Mps* apply_compress(Ctx* ctx, const Mpo* O, const Mps* psi, int D, double cutoff) {
-    Mps* X = mpo_apply(ctx, O, psi);
+    return compress_terms(ctx, {ZipTerm{cplx(1.0, 0.0), O, psi}}, D, cutoff);
+}
+
+Mps* pc_stage(Ctx* ctx, const Mps* psi, const Mpo* O, const Mps* phi, cplx c, int D, double cutoff) {
+    return compress_terms(ctx, {ZipTerm{cplx(1.0, 0.0), nullptr, psi}, ZipTerm{c, O, phi}}, D, cutoff);
+}
+
+Mps* taylor_growth(Ctx* ctx, const Mpo* H, const Mps* psi, double dtau, int D, double cutoff) {
+    Mps* phi = nullptr;
     try {
-        return compress(ctx, X, D, cutoff, true);
+        for (int k = 4; k >= 1; --k) {
+            const Mps* src = phi ? phi : psi;
+            Mps* nxt = compress_terms(ctx, {ZipTerm{cplx(1.0, 0.0), nullptr, psi},
+                                            ZipTerm{cplx(-dtau / k, 0.0), H, src}},
+                                      D, cutoff);
+            mps_free(phi);
+            phi = nxt;
+        }
     } catch (...) {
-        mps_free(X);
+        mps_free(phi);
         throw;
     }
+    return phi;
 }
 
 // ============================================================== overlap

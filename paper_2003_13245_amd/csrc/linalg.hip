@@ -120,7 +120,7 @@ __global__ void triinv_kernel(const double* __restrict__ U, double* __restrict__
 
 // trace of a Hermitian matrix -> shift = c * eps * trace
 __global__ void shift_kernel(const double* G, int n, double c, double* out) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += G[(int64_t)i * n + i];
     s = bsum(s, sh);
@@ -230,7 +230,7 @@ void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L) {
 // Working matrix W is column-major m x n: W[i + j*m], planar (plane = m*n).
 __global__ void hh_colnorm_partial(const double* W, int64_t m, int64_t plane, int j,
                                    double* part) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     const double* col = W + (int64_t)j * m;
     double s = 0.0;
     for (int64_t i = j + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
@@ -245,7 +245,7 @@ __global__ void hh_colnorm_partial(const double* W, int64_t m, int64_t plane, in
 // record [tau_r, tau_i, scale_r, scale_i, beta]
 __global__ void hh_make(double* W, int64_t m, int64_t plane, int j, const double* part, int nb,
                         double* hs) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     double s = 0.0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
     s = bsum(s, sh);
@@ -285,7 +285,7 @@ __global__ void hh_scale(double* W, int64_t m, int64_t plane, int j, const doubl
 }
 // partial w_c = sum_{i>=j} conj(v_i) W[i][c], for c in (j, c1): grid (nb, c1-j-1)
 __global__ void hh_pdot_partial(const double* W, int64_t m, int64_t plane, int j, double* part) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     const int c = j + 1 + blockIdx.y;
     const double* v = W + (int64_t)j * m;
     const double* x = W + (int64_t)c * m;
@@ -314,7 +314,7 @@ __global__ void hh_pdot_partial(const double* W, int64_t m, int64_t plane, int j
 }
 // reduce partials (one block per column) then W[i][c] -= conj(tau) v_i w_c
 __global__ void hh_pdot_reduce(const double* part, int nb, double* wv) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     const int c = blockIdx.x;
     double sr = 0.0, si = 0.0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -453,7 +453,16 @@ __global__ void hh_store_q(const double* Qc, int64_t m, int r, int64_t plane, co
     }
 }
 
-void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, double* R) {
+__global__ void conj_copy_kernel(const double* __restrict__ s, double* __restrict__ d, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        d[i] = s[i];
+        d[i + n] = -s[i + n];
+    }
+}
+
+void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, double* R,
+                    bool adjoint) {
     FTD_CHECK(m >= 1 && n >= 1, FTD_EINVAL, "qr_householder: empty matrix");
     const int r = (int)std::min(m, n);
     const int NBP = 16;
@@ -476,8 +485,13 @@ void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, 
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * 512 * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
     double* wv = ctx->scal + 64;   // up to NBP complex
-    // column-major copy: W = M^T storage-wise (rows m, cols n)
-    k_transpose(ctx, M, m, n, mn, W, mn, 0);
+    // column-major working copy of the m x n matrix being factored: for a
+    // row-major M that is a transpose; for the adjoint of a row-major n x m M
+    // it is the element-wise conjugate of M's storage.
+    if (adjoint)
+        conj_copy_kernel<<<grid1(mn), 256, 0, ctx->stream>>>(M, W, mn);
+    else
+        k_transpose(ctx, M, m, n, mn, W, mn, 0);
     const int nbr = (int)std::min<int64_t>(256, std::max<int64_t>(1, (m + 2047) / 2048));
     std::vector<int> panels;
     for (int p0 = 0; p0 < r; p0 += NBP) panels.push_back(p0);
@@ -532,6 +546,10 @@ void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, 
     // R
     hh_extract_r<<<grid1((int64_t)r * n), 256, 0, ctx->stream>>>(W, m, mn, r, (int)n, hs, R,
                                                                  (int64_t)r * n);
+    if (!Q) {
+        FTD_HIP(hipGetLastError());
+        return;
+    }
     // Q = H_1 ... H_r [I; 0], applying panels last to first
     hh_q_init<<<grid1(mr), 256, 0, ctx->stream>>>(Qc, m, r, mr);
     for (int pi = (int)panels.size() - 1; pi >= 0; --pi) {
@@ -575,8 +593,9 @@ void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, 
 // players, player n2-1 fixed).  U column-major m x n, V column-major n x n.
 __global__ __launch_bounds__(256) void jacobi_round(double* U, int64_t m, int64_t uplane,
                                                     double* V, int n, int64_t vplane, int n2,
-                                                    int rd, double tol, int* rotated) {
-    __shared__ double sh[8];
+                                                    int rd, double tol, const double* fro2,
+                                                    int* rotated) {
+    __shared__ double sh[16];
     __shared__ double rot[4];
     __shared__ int skip;
     const int i = blockIdx.x;
@@ -610,7 +629,9 @@ __global__ __launch_bounds__(256) void jacobi_round(double* U, int64_t m, int64_
     ci = bsum(ci, sh);
     if (threadIdx.x == 0) {
         const double ac = sqrt(cr * cr + ci * ci);
-        if (ac == 0.0 || ac <= tol * sqrt(a * b)) {
+        // columns at rounding level of the whole matrix count as zero
+        const double noise = DBL_EPSILON * DBL_EPSILON * fro2[0];
+        if (ac == 0.0 || ac <= tol * sqrt(a * b) || a <= noise || b <= noise) {
             skip = 1;
         } else {
             skip = 0;
@@ -653,14 +674,21 @@ __global__ __launch_bounds__(256) void jacobi_round(double* U, int64_t m, int64_
     }
 }
 __global__ void count_kernel(const int* f, int n, int* out) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += f[i];
     s = bsum(s, sh);
     if (threadIdx.x == 0) out[0] = (int)s;
 }
+__global__ void fro2_kernel(const double* U, int64_t n, int64_t plane, double* out) {
+    __shared__ double sh[16];
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) s += U[k] * U[k] + U[k + plane] * U[k + plane];
+    s = bsum(s, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
 __global__ void colnorm_kernel(const double* U, int64_t m, int64_t plane, double* S) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     const double* x = U + (int64_t)blockIdx.x * m;
     double s = 0.0;
     for (int64_t k = threadIdx.x; k < m; k += blockDim.x) s += x[k] * x[k] + x[k + plane] * x[k + plane];
@@ -683,14 +711,16 @@ void svd_jacobi(Ctx* ctx, const double* X, int64_t m, int64_t n, double* U, doub
     }
     const int n2 = (int)(n + (n & 1));
     const int npair = n2 / 2;
-    const double tol = DBL_EPSILON * sqrt((double)m);
+    const double tol = 8.0 * DBL_EPSILON * sqrt((double)m);
+    double* fro2 = ctx->scal + 40;
+    fro2_kernel<<<1, 256, 0, ctx->stream>>>(U, mn, mn, fro2);
     ctx->ws_svd2.ensure(ctx, sizeof(int) * (size_t)npair * (n2 - 1) + 64);
     int* rotated = ctx->ws_svd2.as<int>();
     int* cnt = ctx->iscal + 12;
     for (int sweep = 0; sweep < 60; ++sweep) {
         FTD_HIP(hipMemsetAsync(rotated, 0, sizeof(int) * (size_t)npair * (n2 - 1), ctx->stream));
         for (int rd = 0; rd < n2 - 1; ++rd)
-            jacobi_round<<<npair, 256, 0, ctx->stream>>>(U, m, mn, V, (int)n, nn, n2, rd, tol,
+            jacobi_round<<<npair, 256, 0, ctx->stream>>>(U, m, mn, V, (int)n, nn, n2, rd, tol, fro2,
                                                         rotated + (size_t)rd * npair);
         count_kernel<<<1, 256, 0, ctx->stream>>>(rotated, npair * (n2 - 1), cnt);
         FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i + 1, cnt, sizeof(int), hipMemcpyDeviceToHost,

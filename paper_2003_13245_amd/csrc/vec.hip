@@ -103,7 +103,7 @@ void k_zero(Ctx* ctx, void* p, size_t bytes) {
 // --------------------------------------------------------------- reductions
 __global__ void dot_partial(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
                             int64_t plane, double* __restrict__ part) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     double sr = 0.0, si = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -120,7 +120,7 @@ __global__ void dot_partial(const double* __restrict__ x, const double* __restri
 }
 __global__ void nrm2_partial(const double* __restrict__ x, int64_t n, int64_t plane,
                              double* __restrict__ part) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -132,7 +132,7 @@ __global__ void nrm2_partial(const double* __restrict__ x, int64_t n, int64_t pl
 }
 // sum `cnt` groups of `nb` partials, each group `width` wide (interleaved)
 __global__ void sum_partials(const double* __restrict__ part, int nb, int width, double* out) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     const int g = blockIdx.x;
     for (int c = 0; c < width; ++c) {
         double s = 0.0;
@@ -163,7 +163,7 @@ void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out) {
 __global__ void multidot_partial(const double* __restrict__ V, int64_t vstride,
                                  const double* __restrict__ w, int64_t n, int64_t plane,
                                  double* __restrict__ part) {
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     const int j = blockIdx.y;
     const double* v = V + (int64_t)j * vstride;
     double sr = 0.0, si = 0.0;
@@ -246,17 +246,17 @@ template <typename Tin, typename Tout, int MAXD>
 __global__ void chanmix_kernel(const Tin* __restrict__ in, const Tin* __restrict__ ops,
                                Tout* __restrict__ out, const MixParams p) {
     const int d = p.d;
+    const int64_t ldi = p.ldIn ? p.ldIn : p.Db;
+    const int64_t ldo = p.ldOut ? p.ldOut : p.Db;
     const int64_t per = (int64_t)p.Da * d * p.Db;
     const int64_t tot = per * p.njobs;
-    const int64_t sp = (int64_t)d * p.Db;        // stride of p
-    const int64_t sa = (int64_t)d * sp;          // stride of a
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int job = (int)(e / per);
         const int64_t r = e % per;
-        const int a = (int)(r / sp);
-        const int64_t rr = r % sp;             // q*Db + b
-        const int64_t base = a * sa + rr;
+        const int a = (int)(r / ((int64_t)d * p.Db));
+        const int q = (int)((r / p.Db) % d);
+        const int b = (int)(r % p.Db);
         Tin accr[MAXD], acci[MAXD];
 #pragma unroll
         for (int o = 0; o < MAXD; ++o) {
@@ -264,11 +264,11 @@ __global__ void chanmix_kernel(const Tin* __restrict__ in, const Tin* __restrict
             acci[o] = 0;
         }
         for (int en = p.job[job].e0; en < p.job[job].e1; ++en) {
-            const Tin* x = in + p.ent[en].offIn + base;
+            const Tin* x = in + p.ent[en].offIn + ((int64_t)a * d * d + q) * ldi + b;
             const Tin* opr = ops + (int64_t)p.ent[en].op * p.opStride;
             const Tin* opi = opr + (int64_t)d * d;
             for (int pp = 0; pp < d; ++pp) {
-                const Tin xr = x[pp * sp], xi = x[pp * sp + p.planeIn];
+                const Tin xr = x[pp * d * ldi], xi = x[pp * d * ldi + p.planeIn];
 #pragma unroll
                 for (int o = 0; o < MAXD; ++o) {
                     if (o < d) {
@@ -279,16 +279,16 @@ __global__ void chanmix_kernel(const Tin* __restrict__ in, const Tin* __restrict
                 }
             }
         }
-        Tout* y = out + p.job[job].offOut + base;
+        Tout* y = out + p.job[job].offOut + ((int64_t)a * d * d + q) * ldo + b;
 #pragma unroll
         for (int o = 0; o < MAXD; ++o) {
             if (o < d) {
                 if (p.accumulate) {
-                    y[o * sp] += (Tout)accr[o];
-                    y[o * sp + p.planeOut] += (Tout)acci[o];
+                    y[o * d * ldo] += (Tout)accr[o];
+                    y[o * d * ldo + p.planeOut] += (Tout)acci[o];
                 } else {
-                    y[o * sp] = (Tout)accr[o];
-                    y[o * sp + p.planeOut] = (Tout)acci[o];
+                    y[o * d * ldo] = (Tout)accr[o];
+                    y[o * d * ldo + p.planeOut] = (Tout)acci[o];
                 }
             }
         }
@@ -378,7 +378,7 @@ void k_mpo_apply(Ctx* ctx, const double* A, int Da, int d, int Db, const double*
 
 __global__ void embed_kernel(const double* __restrict__ src, int Da, int dd, int Db,
                              double* __restrict__ dst, int DA, int DB, int a0, int b0, double re,
-                             double im) {
+                             double im, int acc) {
     const int64_t n = (int64_t)Da * dd * Db;
     const int64_t N = (int64_t)DA * dd * DB;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
@@ -388,15 +388,21 @@ __global__ void embed_kernel(const double* __restrict__ src, int Da, int dd, int
         const int b = (int)(e % Db);
         const double xr = src[e], xi = src[e + n];
         const int64_t o = (((int64_t)(a + a0)) * dd + s) * DB + (b + b0);
-        dst[o] = re * xr - im * xi;
-        dst[o + N] = re * xi + im * xr;
+        if (acc) {
+            dst[o] += re * xr - im * xi;
+            dst[o + N] += re * xi + im * xr;
+        } else {
+            dst[o] = re * xr - im * xi;
+            dst[o + N] = re * xi + im * xr;
+        }
     }
 }
 void k_embed(Ctx* ctx, const double* src, int Da, int dd, int Db, double* dst, int DA, int DB,
-             int a0, int b0, double re, double im) {
+             int a0, int b0, double re, double im, int accumulate) {
     const int64_t n = (int64_t)Da * dd * Db;
     if (n <= 0) return;
-    embed_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, Da, dd, Db, dst, DA, DB, a0, b0, re, im);
+    embed_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, Da, dd, Db, dst, DA, DB, a0, b0, re,
+                                                        im, accumulate);
     FTD_HIP(hipGetLastError());
 }
 

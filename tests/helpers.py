@@ -54,3 +54,33 @@ def rel(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def mps_inner(a, b):
+    """<a|b> by left-to-right contraction (log_norm factors excluded)."""
+    E = np.ones((1, 1), dtype=complex)
+    for A, B in zip(a.A, b.A):
+        E = np.einsum("xy,xpqa,ypqb->ab", E, A.conj(), B)
+    return complex(E[0, 0])
+
+
+def mps_rel_distance(a, b, n_probe=6, seed=1234):
+    """Relative difference of two MPS through linear probes: for random MPS r
+    of bond dimension 3, max |<r|a> - <r|b>| / max |<r|b>|.  Linear in a - b,
+    so it resolves differences down to rounding (no cancellation)."""
+    rng = np.random.default_rng(seed)
+    dims = [t.shape[1] for t in b.A]
+    L = len(dims)
+    num, den = 0.0, 0.0
+    for _ in range(n_probe):
+        R = []
+        for i, d in enumerate(dims):
+            x = 1 if i == 0 else 3
+            y = 1 if i == L - 1 else 3
+            R.append(rng.standard_normal((x, d, d, y)) + 1j * rng.standard_normal((x, d, d, y)))
+        from oracle.tdvp import MPS
+        r = MPS(R)
+        ra, rb = mps_inner(r, a), mps_inner(r, b)
+        num = max(num, abs(ra - rb))
+        den = max(den, abs(rb))
+    return float(num / den)
