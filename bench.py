@@ -112,7 +112,8 @@ def main():
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--krylov-tol", type=float, default=1e-10)
+    ap.add_argument("--krylov-tol", type=float, default=None,
+                    help="Lanczos stop tolerance (default: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -127,7 +128,8 @@ def main():
     m, r = wl.model, wl.run
     ctx = api.Context(0)
     H, J = api.mpo_build(ctx, m)
-    tol, mmax = args.krylov_tol, 40
+    tol = args.krylov_tol if args.krylov_tol is not None else r.krylov_tol
+    mmax = r.krylov_mmax
 
     log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D})")
     t0 = time.perf_counter()

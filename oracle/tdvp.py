@@ -36,9 +36,21 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.linalg as sla
 from scipy.linalg import eigh_tridiagonal
 
 from . import model as Mdl
+
+# LAPACK driver of the compression SVD.  "gesdd" and "gesvd" compute the same
+# decomposition up to rounding; the tests run the oracle with both to measure
+# how far rounding alone moves C(t) on a given workload.
+SVD_DRIVER = "gesdd"
+
+
+def svd(M):
+    """Thin SVD M = U diag(s) Vh with s descending."""
+    return sla.svd(M, full_matrices=False, lapack_driver=SVD_DRIVER)
+
 
 # --------------------------------------------------------------------------
 # MPS containers
@@ -232,7 +244,7 @@ def svd_compress(X, D, cutoff):
     L = len(A)
     for i in range(L - 1):
         a, d, _, b = A[i].shape
-        U, s, Vh = np.linalg.svd(A[i].reshape(a * d * d, b), full_matrices=False)
+        U, s, Vh = svd(A[i].reshape(a * d * d, b))
         k = truncation_rank(s, D, cutoff)
         A[i] = U[:, :k].reshape(a, d, d, k)
         A[i + 1] = np.tensordot(s[:k, None] * Vh[:k], A[i + 1], axes=([1], [0]))

@@ -84,3 +84,17 @@ def mps_rel_distance(a, b, n_probe=6, seed=1234):
         num = max(num, abs(ra - rb))
         den = max(den, abs(rb))
     return float(num / den)
+
+
+def download_mps(psi_gpu, dims):
+    """Host copy (oracle MPS) of a device MPS, log_norm included."""
+    from oracle import tdvp as T
+    info = psi_gpu.info()
+    bd = info["bond_dims"]
+    L = info["n_sites"]
+    out = []
+    for i in range(L):
+        a = 1 if i == 0 else bd[i - 1]
+        b = 1 if i == L - 1 else bd[i]
+        out.append(psi_gpu.site(i, (a, dims[i], dims[i], b)))
+    return T.MPS(out, info["log_norm"])

@@ -6,6 +6,7 @@ import sys
 import numpy as np
 import pytest
 
+from helpers import download_mps as gpu_tensors
 from helpers import mps_rel_distance, random_mps, rel, small_model
 from oracle import model as Mdl
 from oracle import mpo as OM
@@ -17,18 +18,6 @@ pytestmark = pytest.mark.gpu
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def gpu_tensors(psi_gpu, dims):
-    info = psi_gpu.info()
-    bd = info["bond_dims"]
-    L = info["n_sites"]
-    out = []
-    for i in range(L):
-        a = 1 if i == 0 else bd[i - 1]
-        b = 1 if i == L - 1 else bd[i]
-        out.append(psi_gpu.site(i, (a, dims[i], dims[i], b)))
-    return T.MPS(out, info["log_norm"])
 
 
 MODELS = {
