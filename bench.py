@@ -37,6 +37,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class Roctx:
+    """roctx profiler pause/resume: with `rocprofv3 --selected-regions` only
+    the bracketed regions (the timed steps) are traced.  No-op without the
+    library or without a profiler."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        for path in ("/opt/rocm/lib/librocprofiler-sdk-roctx.so", "librocprofiler-sdk-roctx.so"):
+            try:
+                lib = ctypes.CDLL(path)
+            except OSError:
+                continue
+            if hasattr(lib, "roctxProfilerResume") and hasattr(lib, "roctxProfilerPause"):
+                for f in (lib.roctxProfilerResume, lib.roctxProfilerPause):
+                    f.argtypes = [ctypes.c_uint64]   # roctx_thread_id_t, 0 = whole process
+                    f.restype = ctypes.c_int
+                self.lib = lib
+                break
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
+
+
+def kernel_name(kind):
+    """Name of the GEMM kernel instance with identity `kind` (see ftd_stats)."""
+    tin = "double" if (kind >> 3) == 0 else "float"
+    tout = "double" if (kind & 4) else tin
+    ak = "true" if (kind & 2) else "false"
+    bk = "true" if (kind & 1) else "false"
+    return f"ftd::gemm_kernel<{tin}, {tout}, {ak}, {bk}>"
+
+
 def workload(name):
     from paper_2003_13245_amd import workloads as W
     if name == "headline":
@@ -48,12 +86,14 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_steps(api, ctx, H, J, psi0, phi0, steps, dt, tol, mmax, timing):
+def run_steps(api, ctx, H, J, psi0, phi0, steps, dt, tol, mmax, timing, roctx=None):
     psi, phi = psi0.copy(), phi0.copy()
     C = []
     ctx.stats_reset()
     ctx.set_timing(timing)
     ctx.synchronize()
+    if roctx:
+        roctx.resume()
     t0 = time.perf_counter()
     for _ in range(steps):
         api.tdvp_step(ctx, H, psi, dt_real=dt, tol=tol, mmax=mmax)
@@ -61,6 +101,8 @@ def run_steps(api, ctx, H, J, psi0, phi0, steps, dt, tol, mmax, timing):
         C.append(api.overlap(ctx, psi, J, phi))
     ctx.synchronize()
     t1 = time.perf_counter()
+    if roctx:
+        roctx.pause()
     st = ctx.stats()
     ctx.set_timing(False)
     return np.array(C), t1 - t0, st
@@ -112,6 +154,11 @@ def main():
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after timing, copy this many MiB device-to-device inside its own "
+                         "profiler region (HBM counter calibration)")
+    ap.add_argument("--verbose", type=int, default=1,
+                    help="library progress lines on stderr (0 silent, 2 per compression)")
     ap.add_argument("--krylov-tol", type=float, default=None,
                     help="Lanczos stop tolerance (default: the workload's)")
     args = ap.parse_args()
@@ -127,16 +174,19 @@ def main():
     wl = workload(args.workload)
     m, r = wl.model, wl.run
     ctx = api.Context(0)
+    ctx.set_verbose(args.verbose)
     H, J = api.mpo_build(ctx, m)
     tol = args.krylov_tol if args.krylov_tol is not None else r.krylov_tol
     mmax = r.krylov_mmax
 
     log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D})")
     t0 = time.perf_counter()
-    psi_beta, logz = api.thermal_prep(ctx, H, r.beta, r.n_imag, -1, r.D, cutoff=r.cutoff,
+    psi_beta, logz = api.thermal_prep(ctx, H, r.beta, r.n_imag, r.n_grow, r.D, cutoff=r.cutoff,
                                       precision=args.precision, tol=tol, mmax=mmax)
     t_prep = time.perf_counter() - t0
-    log(f"[bench] prep {t_prep:.1f} s, ln Z = {logz:.6f}, bonds max {max(psi_beta.info()['bond_dims'])}")
+    bonds = psi_beta.info()["bond_dims"]
+    log(f"[bench] prep {t_prep:.1f} s, ln Z = {logz:.6f}, bonds max {max(bonds)} "
+        f"mean {sum(bonds) / len(bonds):.1f}")
     t0 = time.perf_counter()
     phi0 = api.apply_compress(ctx, J, psi_beta, r.D, r.cutoff)
     t_j = time.perf_counter() - t0
@@ -146,7 +196,19 @@ def main():
     # warmup (untimed), then the timed mixed-precision steps
     if args.warmup:
         run_steps(api, ctx, H, J, psi0, phi0, args.warmup, r.dt, tol, mmax, False)
-    C_mix, el_mix, st = run_steps(api, ctx, H, J, psi0, phi0, args.steps, r.dt, tol, mmax, True)
+    roctx = Roctx()
+    C_mix, el_mix, st = run_steps(api, ctx, H, J, psi0, phi0, args.steps, r.dt, tol, mmax, True,
+                                  roctx)
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        roctx.resume()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        roctx.pause()
+        del src, dst
     sps = args.steps / el_mix
     log(f"[bench] mixed: {el_mix / args.steps * 1e3:.1f} ms/step, H_eff "
         f"{st['heff_flops'] / max(st['heff_ms'], 1e-9) / 1e9:.1f} TFLOP/s")
@@ -158,7 +220,9 @@ def main():
         "dtype": args.precision, "data": "synthetic",
         "config": {"workload": wl.name, "n_mol": m.n_mol, "local_modes": m.n_loc,
                    "bond_modes": m.n_nl, "levels": m.levels_loc, "D": r.D,
-                   "T_K": 300.0, "dt_fs": 0.5, "krylov_tol": tol},
+                   "T_K": 300.0, "dt_fs": 0.5, "krylov_tol": tol, "n_imag": r.n_imag,
+                   "n_grow": r.n_grow, "bond_max": max(bonds),
+                   "bond_mean": round(sum(bonds) / len(bonds), 1)},
         "heff_tflops": st["heff_flops"] / max(st["heff_ms"], 1e-9) / 1e9,
         "matvecs_per_step": st["matvecs"] / args.steps,
         "krylov_mean": st["krylov_vectors"] / max(st["expm_calls"], 1),
@@ -168,7 +232,7 @@ def main():
     achieved = st["dom_flops"] / max(st["dom_ms"], 1e-12) / 1e9     # TFLOP/s
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision],
                        "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
-                       "traffic": None, "kernel": "gemm_kernel (H_eff contraction)",
+                       "traffic": None, "kernel": kernel_name(st["dom_kind"]),
                        "avg_launch_ms": dom_avg_ms, "launches": st["dom_launches"]}
     if not args.no_fp64:
         C64, el64, st64 = run_steps(api, ctx, H, J, _as(api, ctx, psi0, "c128"),

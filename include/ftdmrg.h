@@ -107,8 +107,9 @@ const char* ftd_last_error(void);
  * ftd_ctx_stats synchronises and returns, for the contraction kernels of the
  * H_eff / K_eff matvecs since the last reset: number of launches, summed
  * kernel milliseconds and summed algorithmic flops (8 m n k per complex
- * product); and over the whole context the number of matvecs and Krylov
- * vectors.  Statistics are reset by ftd_ctx_stats_reset. */
+ * product); the same for the single GEMM kernel instance with the largest
+ * time share (dom_*, timed without its split-K reduction); and over the
+ * whole context the number of matvecs and Krylov vectors.  Statistics are reset by ftd_ctx_stats_reset. */
 typedef struct {
     int64_t heff_launches;
     double heff_ms;
@@ -121,11 +122,19 @@ typedef struct {
     int64_t krylov_vectors;
     int64_t expm_calls;
     int64_t krylov_max;
+    int32_t dom_kind;          /* identity of that kernel: 8*precision (0 f64,
+                                  1 f32) + 4*(f64 output) + 2*(A k-contiguous)
+                                  + (B k-contiguous) */
 } ftd_stats;
 ftd_status ftd_ctx_set_timing(ftd_ctx* ctx, int32_t enable);
 ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out);
 ftd_status ftd_ctx_stats_reset(ftd_ctx* ctx);
 ftd_status ftd_ctx_synchronize(ftd_ctx* ctx);
+/* Progress log on stderr: level 0 silent (default), 1 one line per
+ * imaginary-time step of ftd_thermal_prep and per real-time step of
+ * ftd_corr_current (wall seconds, largest bond), 2 also one line per
+ * compression phase. */
+ftd_status ftd_ctx_set_verbose(ftd_ctx* ctx, int32_t level);
 
 /* ------------------------------------------------------------------- MPO */
 

@@ -462,20 +462,49 @@ def norm(psi):
 # --------------------------------------------------------------------------
 
 
+def growth_done(before, after, D, full):
+    """Stop rule of adaptive growth (n_grow < 0): stop after a growth step
+    that raised no bond, or raised the summed bond dimension by less than
+    2 %, or left every bond at min(D, its largest possible value)."""
+    if all(b >= min(D, f) for b, f in zip(after, full)):
+        return True
+    if not any(a > b for a, b in zip(after, before)):
+        return True
+    return sum(after) < 1.02 * sum(before)
+
+
+def full_bonds(dims):
+    """Largest possible bond dimension at each bond of a purified MPS."""
+    L = len(dims)
+    left = np.cumprod([float(d) ** 2 for d in dims])
+    right = np.cumprod([float(d) ** 2 for d in dims[::-1]])[::-1]
+    return [min(left[i], right[i + 1]) for i in range(L - 1)]
+
+
 def thermal_prep(model, Hw, beta, n_imag, n_grow, D, cutoff=1e-10, tol=1e-14,
                  mmax=40, stats=None):
-    """|Psi_beta> = exp(-beta H/2)|I> in n_imag steps of beta/(2 n_imag).
+    """|Psi_beta> = exp(-beta H/2)|I> in n_imag steps of beta/(2 n_imag):
+    the first n_grow steps by propagation and compression (n_grow < 0:
+    adaptive, see growth_done), the rest by one-site TDVP.
     Returns the normalised right-canonical state and ln Z."""
     dtau = beta / (2.0 * n_imag)
     psi = identity_mps(model)
     psi = compress(psi, D, cutoff)
     normalize(psi)
-    for _ in range(n_grow):
+    full = full_bonds([t.shape[1] for t in psi.A])
+    steps = 0
+    for _ in range(n_imag if n_grow < 0 else n_grow):
+        before = psi.bond_dims()
         psi = taylor_growth_step(psi, Hw, dtau, D, cutoff)
         normalize(psi)
-    for _ in range(n_imag - n_grow):
+        steps += 1
+        if n_grow < 0 and growth_done(before, psi.bond_dims(), D, full):
+            break
+    for _ in range(n_imag - steps):
         tdvp_step(psi, Hw, -dtau, tol, mmax, stats)
         normalize(psi)
+    if stats is not None:
+        stats.growth_steps = steps
     return psi, 2.0 * psi.log_norm
 
 

@@ -42,7 +42,8 @@ class Stats(C.Structure):
                 ("heff_flops", C.c_double), ("dom_launches", C.c_int64),
                 ("dom_ms", C.c_double), ("dom_flops", C.c_double), ("dom_bytes", C.c_double),
                 ("matvecs", C.c_int64), ("krylov_vectors", C.c_int64),
-                ("expm_calls", C.c_int64), ("krylov_max", C.c_int64)]
+                ("expm_calls", C.c_int64), ("krylov_max", C.c_int64),
+                ("dom_kind", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -64,6 +65,7 @@ SIGNATURES = {
     "ftd_last_error": (C.c_char_p, []),
     "ftd_ctx_create": (I32, [I32, P, C.POINTER(Allocator), PP]),
     "ftd_ctx_destroy": (None, [P]),
+    "ftd_ctx_set_verbose": (I32, [P, I32]),
     "ftd_ctx_set_timing": (I32, [P, I32]),
     "ftd_ctx_stats": (I32, [P, C.POINTER(Stats)]),
     "ftd_ctx_stats_reset": (I32, [P]),

@@ -88,6 +88,9 @@ class Context:
     def set_timing(self, on: bool):
         check(lib.ftd_ctx_set_timing(self.h, int(bool(on))))
 
+    def set_verbose(self, level: int):
+        check(lib.ftd_ctx_set_verbose(self.h, int(level)))
+
     def stats_reset(self):
         check(lib.ftd_ctx_stats_reset(self.h))
 

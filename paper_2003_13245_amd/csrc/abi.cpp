@@ -134,6 +134,13 @@ ftd_status ftd_ctx_set_timing(ftd_ctx* ctx, int32_t enable) {
     });
 }
 
+ftd_status ftd_ctx_set_verbose(ftd_ctx* ctx, int32_t level) {
+    return guarded([&] {
+        FTD_CHECK(ctx, FTD_EINVAL, "null context");
+        ctx->c.verbose = level;
+    });
+}
+
 ftd_status ftd_ctx_stats_reset(ftd_ctx* ctx) {
     return guarded([&] {
         FTD_CHECK(ctx, FTD_EINVAL, "null context");
@@ -165,8 +172,11 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
                 s.heff_flops += e.flops;
             }
             if (e.tag == TAG_HEFF) {
+                // the kernel alone: up to the event after the main launch
+                float kms_one = ms;
+                if (e.m) FTD_HIP(hipEventElapsedTime(&kms_one, e.a, e.m));
                 const int k = e.kind & 63;
-                kms[k] += ms;
+                kms[k] += kms_one;
                 kfl[k] += e.flops;
                 kby[k] += e.bytes;
                 kn[k]++;
@@ -179,6 +189,7 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
         s.dom_ms = kms[best];
         s.dom_flops = kfl[best];
         s.dom_bytes = kby[best];
+        s.dom_kind = best;
         *out = s;
     });
 }
@@ -386,6 +397,12 @@ ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t
         const Prec pr = to_prec(prec);
         Ctx* c = &ctx->c;
         const Mpo* h = H->m;
+        const double t_start = wall_seconds();
+        auto maxb = [](const Mps* m) {
+            int b = 1;
+            for (int i = 0; i + 1 < m->L; ++i) b = std::max(b, m->Dr[i]);
+            return b;
+        };
         Mps* psi = identity_mps(c, h);
         try {
             Mps* t = compress(c, psi, D, cutoff, true);
@@ -403,19 +420,27 @@ ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t
                 psi = nxt;
                 mps_normalize(c, psi);
                 ++steps;
+                vlog(c, 1, "prep growth step %d/%d: max bond %d, %.2f s", steps, n_imag, maxb(psi),
+                     wall_seconds() - t_start);
                 if (adaptive) {
+                    // stop after a step that raised no bond, or raised the summed
+                    // bond dimension by less than 2 %, or left every bond full
                     bool all_full = true, grew = false;
+                    double sum_before = 0.0, sum_after = 0.0;
                     for (int i = 0; i < psi->L - 1; ++i) {
                         if (psi->Dr[i] < std::min<double>(D, mb[i])) all_full = false;
                         if (psi->Dr[i] > before[i]) grew = true;
+                        sum_before += before[i];
+                        sum_after += psi->Dr[i];
                     }
-                    if (all_full || !grew) break;
+                    if (all_full || !grew || sum_after < 1.02 * sum_before) break;
                 }
             }
             psi->prec = pr;
             for (int s = steps; s < n_imag; ++s) {
                 tdvp_step(c, h, psi, cplx(-dtau, 0.0), tol, mmax);
                 mps_normalize(c, psi);
+                vlog(c, 1, "prep tdvp step %d/%d: %.2f s", s + 1, n_imag, wall_seconds() - t_start);
             }
         } catch (...) {
             mps_free(psi);
@@ -484,8 +509,10 @@ ftd_status ftd_corr_current(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mpo* J,
         Mps* psi = mps_clone(psi_beta->m);
         Mps* phi = nullptr;
         try {
+            const double t_start = wall_seconds();
             psi->log_norm = 0.0;
             phi = apply_compress(c, J->m, psi, D, cutoff);
+            vlog(c, 1, "corr: j|psi> compressed, %.2f s", wall_seconds() - t_start);
             phi->prec = psi->prec;
             phi->log_norm = 0.0;
             cplx c0 = overlap(c, psi, J->m, phi);
@@ -497,6 +524,7 @@ ftd_status ftd_corr_current(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mpo* J,
                 cplx ck = overlap(c, psi, J->m, phi);
                 C_out[2 * k] = ck.real();
                 C_out[2 * k + 1] = ck.imag();
+                vlog(c, 1, "corr step %d/%d: %.2f s", k, n_steps, wall_seconds() - t_start);
             }
         } catch (...) {
             mps_free(psi);

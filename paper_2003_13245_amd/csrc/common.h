@@ -3,7 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
 #include <complex>
 #include <cstdint>
 #include <cstring>
@@ -13,6 +16,12 @@
 #include "../../include/ftdmrg.h"
 
 namespace ftd {
+
+inline double wall_seconds() {
+    using clk = std::chrono::steady_clock;
+    return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
 
 using cplx = std::complex<double>;
 
@@ -178,7 +187,7 @@ void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, 
 // Thin SVD of X (m x n, row-major, m >= n) by one-sided Jacobi:
 // X = U S V^H, U m x n (columns scaled), S[n] sorted descending, V n x n.
 void svd_jacobi(Ctx* ctx, const double* X, int64_t m, int64_t n, double* U, double* S,
-                double* V);
+                double* V, bool adjoint_input = false);
 
 // ----------------------------------------------------------------- objects
 struct MpoEntry {
@@ -214,6 +223,7 @@ struct Mps {
 
 struct EventPair {
     hipEvent_t a, b;
+    hipEvent_t m;   // after the main kernel (before a split-K reduction), or null
     double flops, bytes;
     int tag;
     int kind;   // kernel identity for dominant-kernel attribution
@@ -226,6 +236,7 @@ struct Ctx {
     ftd_allocator alloc{};
     // timing
     bool timing = false;
+    int verbose = 0;
     std::vector<EventPair> events;
     std::vector<hipEvent_t> event_pool;
     size_t event_next = 0;
@@ -246,9 +257,21 @@ struct Ctx {
     KrylovDev kd{};
 };
 
+// Progress line on stderr when the context's verbose level is >= level.
+inline void vlog(const Ctx* ctx, int level, const char* fmt, ...) {
+    if (ctx->verbose < level) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fputs("[ftdmrg] ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    std::fputc('\n', stderr);
+    std::fflush(stderr);
+    va_end(ap);
+}
+
 hipEvent_t timing_event(Ctx* ctx);
 void record_kernel(Ctx* ctx, hipEvent_t a, hipEvent_t b, double flops, double bytes, int tag,
-                   int kind);
+                   int kind, hipEvent_t mid = nullptr);
 
 // ---------------------------------------------------------- high level ops
 Mpo* build_mpo(Ctx* ctx, const ftd_model& m, bool current);

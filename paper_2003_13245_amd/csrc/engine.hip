@@ -62,8 +62,8 @@ hipEvent_t timing_event(Ctx* ctx) {
     return ctx->event_pool[ctx->event_next++];
 }
 void record_kernel(Ctx* ctx, hipEvent_t a, hipEvent_t b, double flops, double bytes, int tag,
-                   int kind) {
-    ctx->events.push_back({a, b, flops, bytes, tag, kind});
+                   int kind, hipEvent_t mid) {
+    ctx->events.push_back({a, b, mid, flops, bytes, tag, kind});
 }
 
 // ============================================================ small kernels
@@ -811,8 +811,9 @@ static int truncation_rank(const std::vector<double>& s, int D, double cutoff) {
 // Truncated SVD of T (m x n, row-major, split planes m*n):
 //   T ~ Lq diag(S) Rq,  Lq m x k (orthonormal columns), Rq k x n (orthonormal
 //   rows), k from truncation_rank.  S is multiplied into Lq (s_left) or Rq.
-// Tall blocks (m >= 2n) are reduced by Householder QR first; the small factor
-// is diagonalised by one-sided Jacobi.  Returns newly allocated buffers.
+// Tall blocks (m >= 2n) are reduced by Householder QR first and one-sided
+// Jacobi runs on the adjoint of the triangular factor; otherwise on T (m >= n)
+// or T^H (m < n).  Returns newly allocated buffers.
 TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, double cutoff,
                           bool s_left) {
     const int64_t ns = std::min(m, n);
@@ -861,11 +862,13 @@ TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, doubl
             double* Q = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * n));
             double* R = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * n));
             qr_householder(ctx, T, m, n, Q, R);
-            svd_jacobi(ctx, R, n, n, Ub, Sd, Vb);       // R = U' S V'^H, Ub = U' S
+            // Jacobi on R^H (faster convergence after QR): R^H V' = U' S, so
+            // R = V' S U'^H: left vectors V', right vectors U' = Ub / S
+            svd_jacobi(ctx, R, n, n, Ub, Sd, Vb, true);
             finish();
             upload();
             double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * k));
-            gather(Ub, n, n * n, s_left ? nullptr : dInv, 0, G);
+            gather(Vb, n, n * n, s_left ? dS : nullptr, 0, G);
             o.Lq = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * k));
             GemmParams p{};
             p.M = (int)m; p.N = k; p.K = (int)n;
@@ -875,7 +878,7 @@ TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, doubl
             p.nprob = 1; p.prob[0].t1 = 1;
             gemm(ctx, Prec::F64, true, Q, G, o.Lq, p, TAG_NONE);
             o.Rq = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * k));
-            gather(Vb, n, n * n, s_left ? nullptr : dS, 1, o.Rq);
+            gather(Ub, n, n * n, s_left ? dInv : nullptr, 1, o.Rq);
             FTD_HIP(hipStreamSynchronize(ctx->stream));
             dev_free(ctx, Q);
             dev_free(ctx, R);
@@ -1128,6 +1131,10 @@ static Mps* compress_terms(Ctx* ctx, const std::vector<ZipTerm>& terms, int D, d
     std::vector<int> rk(L, 0);
     Mps* Y = nullptr;
     double* C = nullptr;
+    const double t0 = wall_seconds();
+    double t1 = t0, t_svd = 0.0;
+    int wmax = 0;
+    for (auto& b : bonds) wmax = std::max<int>(wmax, (int)b.width);
     try {
         {
             std::vector<double> ones(2 * nt, 0.0);
@@ -1156,6 +1163,7 @@ static Mps* compress_terms(Ctx* ctx, const std::vector<ZipTerm>& terms, int D, d
             dev_free(ctx, Rp);
             rk[s - 1] = (int)rr;
         }
+        t1 = wall_seconds();
         // 2. left-to-right truncation of the true centre matrices
         Y = new Mps();
         Y->ctx = ctx;
@@ -1204,7 +1212,9 @@ static Mps* compress_terms(Ctx* ctx, const std::vector<ZipTerm>& terms, int D, d
                 p.nprob = 1; p.prob[0].t1 = 1;
                 gemm(ctx, Prec::F64, true, T, Rf[i], P, p, TAG_NONE);
             }
+            const double ts = ctx->verbose >= 2 ? wall_seconds() : 0.0;
             TruncOut tr = svd_trunc(ctx, P, m, r, D, cutoff, false);
+            if (ctx->verbose >= 2) t_svd += wall_seconds() - ts;
             const int k = tr.k;
             double* Cn = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * (int64_t)k * ncols));
             {
@@ -1235,9 +1245,12 @@ static Mps* compress_terms(Ctx* ctx, const std::vector<ZipTerm>& terms, int D, d
         throw;
     }
     for (auto p : Rf) dev_free(ctx, p);
+    const double t2 = wall_seconds();
     // 3. back to right-canonical form
     lq_sweep(ctx, Y);
     FTD_HIP(hipStreamSynchronize(ctx->stream));
+    vlog(ctx, 2, "compress %d terms, widest bond %d: metric %.3f s, truncation %.3f s "
+         "(svd %.3f s), lq sweep %.3f s", nt, wmax, t1 - t0, t2 - t1, t_svd, wall_seconds() - t2);
     return Y;
 }
 

@@ -234,7 +234,7 @@ __global__ void gemm_reduce_kernel(const Tin* __restrict__ partial, Tout* __rest
 
 template <typename Tin, typename Tout>
 static void launch(Ctx* ctx, const void* A, const void* B, void* C, const GemmParams& p,
-                   dim3 grid, Tin* partial) {
+                   dim3 grid, Tin* partial, hipEvent_t mid) {
     const Tin* a = static_cast<const Tin*>(A);
     const Tin* b = static_cast<const Tin*>(B);
     Tout* c = static_cast<Tout*>(C);
@@ -246,6 +246,7 @@ static void launch(Ctx* ctx, const void* A, const void* B, void* C, const GemmPa
         gemm_kernel<Tin, Tout, false, true><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
     else
         gemm_kernel<Tin, Tout, false, false><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    if (mid) FTD_HIP(hipEventRecord(mid, ctx->stream));
     if (p.ksplit > 1) {
         const int64_t tot = (int64_t)p.M * p.N * p.nprob;
         int nb = (int)std::min<int64_t>((tot + 255) / 256, 4096);
@@ -282,18 +283,19 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
         partial = ctx->ws_gemm_partial.p;
     }
     dim3 grid(tn, tm, p.nprob * ks);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, em = nullptr;
     if (ctx->timing && tag != TAG_NONE) {
         e0 = timing_event(ctx);
+        em = timing_event(ctx);
         FTD_HIP(hipEventRecord(e0, ctx->stream));
     }
     if (prec == Prec::F64) {
         FTD_CHECK(out_f64, FTD_EINVAL, "gemm: f64 inputs need f64 output");
-        launch<double, double>(ctx, A, B, C, p, grid, static_cast<double*>(partial));
+        launch<double, double>(ctx, A, B, C, p, grid, static_cast<double*>(partial), em);
     } else if (out_f64) {
-        launch<float, double>(ctx, A, B, C, p, grid, static_cast<float*>(partial));
+        launch<float, double>(ctx, A, B, C, p, grid, static_cast<float*>(partial), em);
     } else {
-        launch<float, float>(ctx, A, B, C, p, grid, static_cast<float*>(partial));
+        launch<float, float>(ctx, A, B, C, p, grid, static_cast<float*>(partial), em);
     }
     FTD_HIP(hipGetLastError());
     if (e0) {
@@ -308,7 +310,7 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
                              (double)p.nprob * p.M * p.N * osz * (p.accumulate ? 2.0 : 1.0);
         // kernel identity: precision x operand layout
         const int kind = (int)prec * 8 + (out_f64 ? 4 : 0) + p.a_kcontig * 2 + p.b_kcontig;
-        record_kernel(ctx, e0, e1, flops, bytes, tag, kind);
+        record_kernel(ctx, e0, e1, flops, bytes, tag, kind, em);
     }
 }
 

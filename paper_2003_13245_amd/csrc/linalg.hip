@@ -11,6 +11,8 @@
 //    small reduction kernels, trailing columns with GEMMs.
 //  * svd_jacobi: one-sided (Hestenes) Jacobi with a round-robin pairing, one
 //    launch per round, every column pair in its own workgroup.
+#include <hip/hip_cooperative_groups.h>
+
 #include "common.h"
 
 #include <algorithm>
@@ -589,17 +591,68 @@ void qr_householder(Ctx* ctx, const double* M, int64_t m, int64_t n, double* Q, 
 }
 
 // ------------------------------------------------------------------ Jacobi
-// One round of one-sided Jacobi: pair i of round rd (circle method over n2
-// players, player n2-1 fixed).  U column-major m x n, V column-major n x n.
-__global__ __launch_bounds__(256) void jacobi_round(double* U, int64_t m, int64_t uplane,
-                                                    double* V, int n, int64_t vplane, int n2,
-                                                    int rd, double tol, const double* fro2,
-                                                    int* rotated) {
-    __shared__ double sh[16];
-    __shared__ double rot[4];
-    __shared__ int skip;
-    const int i = blockIdx.x;
-    int p, q;
+// Sum over the 64 lanes of a wavefront; every lane receives the total (xor
+// butterfly), so all lanes derive the same rotation without a broadcast.
+__device__ __forceinline__ double wave_allsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+constexpr int kJacobiWaves = 4;   // wavefronts per 256-thread block
+
+// Rotation of column pair (p, q) of one-sided Jacobi; returns 1 if rotated.
+// One wavefront; U column-major m x n, V column-major n x n.
+__device__ __forceinline__ int jacobi_pair(double* U, int64_t m, int64_t uplane, double* V, int n,
+                                           int64_t vplane, int p, int q, double tol,
+                                           double noise, int lane) {
+    double* x = U + (int64_t)p * m;
+    double* y = U + (int64_t)q * m;
+    double a = 0.0, b = 0.0, cr = 0.0, ci = 0.0;
+    for (int64_t k = lane; k < m; k += 64) {
+        const double xr = x[k], xi = x[k + uplane], yr = y[k], yi = y[k + uplane];
+        a += xr * xr + xi * xi;
+        b += yr * yr + yi * yi;
+        cr += xr * yr + xi * yi;
+        ci += xr * yi - xi * yr;
+    }
+    a = wave_allsum(a);
+    b = wave_allsum(b);
+    cr = wave_allsum(cr);
+    ci = wave_allsum(ci);
+    const double ac = sqrt(cr * cr + ci * ci);
+    // columns at rounding level of the whole matrix count as zero
+    if (ac == 0.0 || ac <= tol * sqrt(a * b) || a <= noise || b <= noise) return 0;
+    const double zeta = (b - a) / (2.0 * ac);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + t * t);
+    const double sn = t * cs;
+    const double er = cr / ac, ei = -ci / ac;   // e^{-i phi}
+    for (int64_t k = lane; k < m; k += 64) {
+        const double xr = x[k], xi = x[k + uplane];
+        const double y0r = y[k], y0i = y[k + uplane];
+        const double yr = y0r * er - y0i * ei, yi = y0r * ei + y0i * er;   // y e^{-i phi}
+        x[k] = cs * xr - sn * yr;
+        x[k + uplane] = cs * xi - sn * yi;
+        y[k] = sn * xr + cs * yr;
+        y[k + uplane] = sn * xi + cs * yi;
+    }
+    double* vx = V + (int64_t)p * n;
+    double* vy = V + (int64_t)q * n;
+    for (int k = lane; k < n; k += 64) {
+        const double xr = vx[k], xi = vx[k + vplane];
+        const double y0r = vy[k], y0i = vy[k + vplane];
+        const double yr = y0r * er - y0i * ei, yi = y0r * ei + y0i * er;
+        vx[k] = cs * xr - sn * yr;
+        vx[k + vplane] = cs * xi - sn * yi;
+        vy[k] = sn * xr + cs * yr;
+        vy[k + vplane] = sn * xi + cs * yi;
+    }
+    return 1;
+}
+
+// Pair i of round rd in the circle method over n2 players (player n2-1 fixed);
+// the lower index first.
+__device__ __forceinline__ void round_pair(int i, int rd, int n2, int& p, int& q) {
     if (i == 0) {
         p = rd % (n2 - 1);
         q = n2 - 1;
@@ -612,67 +665,32 @@ __global__ __launch_bounds__(256) void jacobi_round(double* U, int64_t m, int64_
         p = q;
         q = t;
     }
-    if (q >= n) return;   // dummy player
-    const double* x = U + (int64_t)p * m;
-    const double* y = U + (int64_t)q * m;
-    double a = 0.0, b = 0.0, cr = 0.0, ci = 0.0;
-    for (int64_t k = threadIdx.x; k < m; k += blockDim.x) {
-        const double xr = x[k], xi = x[k + uplane], yr = y[k], yi = y[k + uplane];
-        a += xr * xr + xi * xi;
-        b += yr * yr + yi * yi;
-        cr += xr * yr + xi * yi;
-        ci += xr * yi - xi * yr;
-    }
-    a = bsum(a, sh);
-    b = bsum(b, sh);
-    cr = bsum(cr, sh);
-    ci = bsum(ci, sh);
-    if (threadIdx.x == 0) {
-        const double ac = sqrt(cr * cr + ci * ci);
-        // columns at rounding level of the whole matrix count as zero
-        const double noise = DBL_EPSILON * DBL_EPSILON * fro2[0];
-        if (ac == 0.0 || ac <= tol * sqrt(a * b) || a <= noise || b <= noise) {
-            skip = 1;
-        } else {
-            skip = 0;
-            const double zeta = (b - a) / (2.0 * ac);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + t * t);
-            const double sn = t * cs;
-            rot[0] = cs;
-            rot[1] = sn;
-            rot[2] = cr / ac;    // e^{i phi}
-            rot[3] = ci / ac;
-            rotated[i] = 1;
-        }
-    }
-    __syncthreads();
-    if (skip) return;
-    const double cs = rot[0], sn = rot[1];
-    const double er = rot[2], ei = -rot[3];   // e^{-i phi}
-    double* xw = U + (int64_t)p * m;
-    double* yw = U + (int64_t)q * m;
-    for (int64_t k = threadIdx.x; k < m; k += blockDim.x) {
-        const double xr = xw[k], xi = xw[k + uplane];
-        const double y0r = yw[k], y0i = yw[k + uplane];
-        const double yr = y0r * er - y0i * ei, yi = y0r * ei + y0i * er;   // y e^{-i phi}
-        xw[k] = cs * xr - sn * yr;
-        xw[k + uplane] = cs * xi - sn * yi;
-        yw[k] = sn * xr + cs * yr;
-        yw[k + uplane] = sn * xi + cs * yi;
-    }
-    double* vx = V + (int64_t)p * n;
-    double* vy = V + (int64_t)q * n;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const double xr = vx[k], xi = vx[k + vplane];
-        const double y0r = vy[k], y0i = vy[k + vplane];
-        const double yr = y0r * er - y0i * ei, yi = y0r * ei + y0i * er;
-        vx[k] = cs * xr - sn * yr;
-        vx[k + vplane] = cs * xi - sn * yi;
-        vy[k] = sn * xr + cs * yr;
-        vy[k + vplane] = sn * xi + cs * yi;
-    }
 }
+
+// One full sweep (all n2-1 rounds) in one cooperative launch: the rounds are
+// separated by grid-wide barriers; each wavefront takes pairs i = its global
+// wave index + k * (total waves).  Adds the number of rotations to *count.
+__global__ __launch_bounds__(64 * kJacobiWaves) void jacobi_sweep(
+    double* U, int64_t m, int64_t uplane, double* V, int n, int64_t vplane, int n2, double tol,
+    const double* fro2, int* count) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kJacobiWaves + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * kJacobiWaves;
+    const int npair = n2 / 2;
+    const double noise = DBL_EPSILON * DBL_EPSILON * fro2[0];
+    int rotated = 0;
+    for (int rd = 0; rd < n2 - 1; ++rd) {
+        for (int i = wave; i < npair; i += nwaves) {
+            int p, q;
+            round_pair(i, rd, n2, p, q);
+            if (q < n) rotated += jacobi_pair(U, m, uplane, V, n, vplane, p, q, tol, noise, lane);
+        }
+        grid.sync();
+    }
+    if (lane == 0 && rotated) atomicAdd(count, rotated);
+}
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
 __global__ void count_kernel(const int* f, int n, int* out) {
     __shared__ double sh[16];
     double s = 0.0;
@@ -696,13 +714,19 @@ __global__ void colnorm_kernel(const double* U, int64_t m, int64_t plane, double
     if (threadIdx.x == 0) S[blockIdx.x] = sqrt(s);
 }
 
-// X row-major m x n (m >= n).  Outputs (column-major): U m x n with columns
-// u_j * s_j (unnormalised), S[n] (unsorted), V n x n.
+// X row-major m x n (m >= n), or with adjoint_input a row-major n x n R
+// whose adjoint is diagonalised (U starts as R^H).  Outputs (column-major):
+// U m x n with columns u_j * s_j (unnormalised), S[n] (unsorted), V n x n,
+// so that (X or R^H) V = U.
 void svd_jacobi(Ctx* ctx, const double* X, int64_t m, int64_t n, double* U, double* S,
-                double* V) {
+                double* V, bool adjoint_input) {
     FTD_CHECK(m >= n && n >= 1, FTD_EINVAL, "svd_jacobi: needs m >= n >= 1");
+    FTD_CHECK(!adjoint_input || m == n, FTD_EINVAL, "svd_jacobi: adjoint input must be square");
     const int64_t mn = m * n, nn = n * n;
-    k_transpose(ctx, X, m, n, mn, U, mn, 0);
+    if (adjoint_input)
+        conj_copy_kernel<<<grid1(mn), 256, 0, ctx->stream>>>(X, U, mn);
+    else
+        k_transpose(ctx, X, m, n, mn, U, mn, 0);
     eye_kernel<<<grid1(nn), 256, 0, ctx->stream>>>(V, (int)n, nn);
     if (n == 1) {
         colnorm_kernel<<<1, 256, 0, ctx->stream>>>(U, m, mn, S);
@@ -714,15 +738,22 @@ void svd_jacobi(Ctx* ctx, const double* X, int64_t m, int64_t n, double* U, doub
     const double tol = 8.0 * DBL_EPSILON * sqrt((double)m);
     double* fro2 = ctx->scal + 40;
     fro2_kernel<<<1, 256, 0, ctx->stream>>>(U, mn, mn, fro2);
-    ctx->ws_svd2.ensure(ctx, sizeof(int) * (size_t)npair * (n2 - 1) + 64);
-    int* rotated = ctx->ws_svd2.as<int>();
+    // co-resident grid for the cooperative sweep
+    int per_cu = 0, cus = 0;
+    FTD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jacobi_sweep, 64 * kJacobiWaves,
+                                                         0));
+    FTD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int max_blocks = std::max(1, per_cu * cus);
+    const int nblk = std::max(1, std::min((npair + kJacobiWaves - 1) / kJacobiWaves, max_blocks));
     int* cnt = ctx->iscal + 12;
     for (int sweep = 0; sweep < 60; ++sweep) {
-        FTD_HIP(hipMemsetAsync(rotated, 0, sizeof(int) * (size_t)npair * (n2 - 1), ctx->stream));
-        for (int rd = 0; rd < n2 - 1; ++rd)
-            jacobi_round<<<npair, 256, 0, ctx->stream>>>(U, m, mn, V, (int)n, nn, n2, rd, tol, fro2,
-                                                        rotated + (size_t)rd * npair);
-        count_kernel<<<1, 256, 0, ctx->stream>>>(rotated, npair * (n2 - 1), cnt);
+        set_int_kernel<<<1, 1, 0, ctx->stream>>>(cnt, 0);
+        int nn_ = (int)n;
+        int64_t m_ = m, mn_ = mn, nn2 = nn;
+        double tol_ = tol;
+        void* args[] = {&U, &m_, &mn_, &V, &nn_, &nn2, (void*)&n2, &tol_, &fro2, &cnt};
+        FTD_HIP(hipLaunchCooperativeKernel((const void*)jacobi_sweep, dim3(nblk),
+                                           dim3(64 * kJacobiWaves), args, 0, ctx->stream));
         FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i + 1, cnt, sizeof(int), hipMemcpyDeviceToHost,
                                ctx->stream));
         FTD_HIP(hipStreamSynchronize(ctx->stream));

@@ -55,6 +55,8 @@ CASES = {
     "tiny_pc_cut6": dict(wl="tiny", n_imag=20, n_grow=20, steps=20, cutoff=1e-6),
     # one growth step, then one-site TDVP in imaginary time
     "tiny_tdvp": dict(wl="tiny", n_imag=20, n_grow=1, steps=10, cutoff=1e-10),
+    # adaptive growth (stops by the growth rule), then one-site TDVP
+    "tiny_adaptive": dict(wl="tiny", n_imag=20, n_grow=-1, steps=10, cutoff=1e-10),
     # Holstein-Peierls ring
     "peierls": dict(wl="peierls", n_imag=6, n_grow=6, steps=10, cutoff=1e-10),
 }

@@ -16,7 +16,7 @@ def graded(rng, M, N, rank, decay=0.5):
 
 @pytest.mark.parametrize("M,N,rank,D", [(40, 10, 10, 4), (15, 10, 10, 6), (10, 40, 10, 3),
                                         (64, 24, 9, 12), (7, 7, 7, 7), (300, 40, 40, 16),
-                                        (24, 96, 20, 8)])
+                                        (24, 96, 20, 8), (900, 301, 301, 64)])
 @pytest.mark.parametrize("s_left", [True, False])
 def test_svd_trunc(ctx, M, N, rank, D, s_left):
     from paper_2003_13245_amd import api

@@ -365,3 +365,32 @@ def test_workloads_are_seeded_and_in_range():
     assert abs(W.fs(0.5) - 20.67) < 0.01
     c2 = W.fp64_chain()
     assert all(0.2 <= g * g <= 1.0 for g in c2.model.g_loc)
+
+
+def test_adaptive_growth_rule():
+    """Stop rule of adaptive growth: no bond raised, < 2 % summed growth, or
+    every bond full."""
+    from oracle import tdvp as T
+    full = [4, 16, 16, 4]
+    assert T.growth_done([2, 2, 2, 2], [4, 16, 16, 4], 32, full)          # all full
+    assert not T.growth_done([2, 2, 2, 2], [4, 8, 8, 4], 32, full)        # grew a lot
+    assert T.growth_done([4, 8, 8, 4], [4, 8, 8, 4], 32, full)            # no bond raised
+    assert T.growth_done([4, 100, 100, 4], [4, 100, 100, 5], 128, [4, 900, 900, 36])
+    assert not T.growth_done([4, 60, 60, 4], [4, 64, 64, 4], 128, [4, 900, 900, 36])
+    assert T.full_bonds([2, 3, 2]) == [4, 4]
+
+
+def test_adaptive_growth_matches_fixed_count():
+    """The adaptive preparation equals the fixed-count one with the number of
+    growth steps it chose (same state, same ln Z)."""
+    from oracle import tdvp as T
+    from paper_2003_13245_amd import workloads as W
+    wl = W.tiny_fp64()
+    m, r = wl.model, wl.run
+    Hw = OM.hamiltonian_mpo(m)
+    st = T.Stats()
+    psi_a, lz_a = T.thermal_prep(m, Hw, r.beta, 6, -1, 8, stats=st)
+    assert 1 <= st.growth_steps < 6
+    psi_f, lz_f = T.thermal_prep(m, Hw, r.beta, 6, st.growth_steps, 8)
+    assert psi_a.bond_dims() == psi_f.bond_dims()
+    assert abs(lz_a - lz_f) < 1e-13
