@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-grow", type=int, default=None,
+                    help="growth steps of the preparation (default: the workload's; <0 adaptive)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device inside its own "
                          "profiler region (HBM counter calibration)")
@@ -173,6 +175,8 @@ def main():
 
     wl = workload(args.workload)
     m, r = wl.model, wl.run
+    if args.n_grow is not None:
+        r.n_grow = args.n_grow
     ctx = api.Context(0)
     ctx.set_verbose(args.verbose)
     H, J = api.mpo_build(ctx, m)

@@ -89,6 +89,7 @@ struct GemmParams {
     int conjA, conjB, accumulate;
     int nprob, ksplit;
     int a_kcontig, b_kcontig;
+    const int* stop;   // launch is a no-op when *stop != 0 (Krylov halt), may be null
     GemmProb prob[kMaxProbs];
     GemmTerm term[kMaxTerms];
 };
@@ -119,6 +120,7 @@ struct MixParams {
     int64_t opStride;   // elements per op (re plane then im plane, d*d each)
     int accumulate;
     int njobs;
+    const int* stop;   // launch is a no-op when *stop != 0, may be null
     MixJob job[kMaxMixJobs];
     MixEnt ent[kMaxMixEnts];
 };
@@ -165,19 +167,22 @@ struct KrylovDev {
     double* h;       // complex [2*(kMaxKrylov+1)]
     double* u;       // complex [2*kMaxKrylov]
     double* nrm;     // [4]
-    int* flag;       // [4]: converged, k, failed
+    int* flag;       // [4]: converged, k, failed, halt (converged or failed)
 };
 void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
                     int exhausted);
 void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane);
 void k_set_alpha(Ctx* ctx, KrylovDev kd, int k);
+void k_krylov_reset(Ctx* ctx, KrylovDev kd);
 
 // ----------------------------------------------------------------- QR / SVD
 // Shifted CholeskyQR (three passes) of a full-column-rank M (m x n, row-major,
 // split planes).  Q overwrites M; R (n x n upper, row-major, planar) returned.
-void qr_chol(Ctx* ctx, double* M, int64_t m, int64_t n, double* R);
+void qr_chol(Ctx* ctx, double* M, int64_t m, int64_t n, double* R, bool check = true);
 // LQ of a full-row-rank M (n x m row-major): M = L Q, Q overwrites M, L n x n.
-void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L);
+void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L, bool check = true);
+// reads and clears the sticky CholeskyQR breakdown flag; throws if it was set
+void chol_flag_check(Ctx* ctx);
 // Householder QR for any rank of an m x n matrix A: Q (m x r, row-major, not
 // formed when Q is null) and R (r x n, row-major), r = min(m, n), diag(R)
 // real >= 0.  A = M (row-major m x n), or A = M^H for a row-major n x m M
@@ -255,6 +260,11 @@ struct Ctx {
     int* h_pinned_i = nullptr;    // host pinned readback
     double* h_pinned_d = nullptr;
     KrylovDev kd{};
+    // While a Krylov exponential is being enqueued: its halt flag.  The
+    // kernels of one Lanczos iteration return at once when it is set, so
+    // iterations can be queued ahead of the convergence test.
+    const int* kstop = nullptr;
+    int krylov_hint[2] = {4, 4};   // recent vector counts (site, bond)
 };
 
 // Progress line on stderr when the context's verbose level is >= level.

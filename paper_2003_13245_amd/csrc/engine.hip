@@ -586,44 +586,77 @@ static void env_right_update(Ctx* ctx, Prec prec, const MpoSite& W, int Da, int 
 // ================================================================ Krylov
 // x <- exp(z Op) x by Lanczos with full (twice-applied classical
 // Gram-Schmidt) reorthogonalisation in float64.
+// exp(z H) x for the Hermitian operator `op`, by Lanczos with full
+// reorthogonalisation (classical Gram-Schmidt applied twice) and the device
+// tridiagonal exponential.  Iterations are enqueued without waiting; every
+// kernel of an iteration returns at once after the device has raised the halt
+// flag, so the host reads the flags only from the expected vector count on
+// (hint: the count of the previous call of the same kind).  Timing events and
+// matvec counts of iterations that ran as no-ops are discarded.
 static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*)>& op, double* x,
-                       int64_t n, cplx z, double tol, int mmax) {
+                       int64_t n, cplx z, double tol, int mmax, int kind) {
     FTD_CHECK(mmax >= 1 && mmax < kMaxKrylov, FTD_EINVAL, "Krylov mmax out of range");
     const int64_t vs = 2 * n;
     ctx->ws_Krylov.ensure(ctx, sizeof(double) * (size_t)vs * (mmax + 1));
     double* V = ctx->ws_Krylov.as<double>();
     KrylovDev kd = ctx->kd;
+    k_krylov_reset(ctx, kd);
     k_nrm2(ctx, x, n, n, kd.nrm + 1);
     k_copy_f64(ctx, x, V, vs);
     k_scale_by_dev(ctx, V, n, n, kd.nrm + 1, 0);
     const int kmax = (int)std::min<int64_t>(mmax, n);
-    for (int k = 0; k < kmax; ++k) {
-        double* vk = V + (int64_t)k * vs;
-        double* w = V + (int64_t)(k + 1) * vs;
-        op(vk, w);
-        k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
-        k_set_alpha(ctx, kd, k);
-        k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
-        k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
-        k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
-        k_nrm2(ctx, w, n, n, kd.nrm);
-        const int exhausted = (k + 1 == n) ? 1 : 0;
-        k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted);
-        k_lanczos_post(ctx, kd, k + 1, w, n, n);
-        FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i, kd.flag, 3 * sizeof(int), hipMemcpyDeviceToHost,
-                               ctx->stream));
-        FTD_HIP(hipStreamSynchronize(ctx->stream));
-        const int conv = ctx->h_pinned_i[0], failed = ctx->h_pinned_i[2];
-        FTD_CHECK(!failed || conv, FTD_ENOCONV, "Krylov exponential: non-finite values");
-        if (conv) {
-            k_lincomb(ctx, V, vs, k + 1, kd.u, kd.nrm + 1, x, n, n);
-            ctx->stats.krylov_vectors += k + 1;
-            ctx->stats.expm_calls += 1;
-            ctx->stats.krylov_max = std::max<int64_t>(ctx->stats.krylov_max, k + 1);
-            return k + 1;
+    const int hint = std::max(1, ctx->krylov_hint[kind] - 1);
+    std::vector<size_t> ev_mark(kmax + 1);
+    std::vector<int64_t> mv_mark(kmax + 1);
+    ctx->kstop = kd.flag + 3;
+    int done = 0;
+    try {
+        for (int k = 0; k < kmax; ++k) {
+            ev_mark[k] = ctx->events.size();
+            mv_mark[k] = ctx->stats.matvecs;
+            double* vk = V + (int64_t)k * vs;
+            double* w = V + (int64_t)(k + 1) * vs;
+            op(vk, w);
+            k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
+            k_set_alpha(ctx, kd, k);
+            k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
+            k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
+            k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
+            k_nrm2(ctx, w, n, n, kd.nrm);
+            const int exhausted = (k + 1 == n) ? 1 : 0;
+            k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted);
+            k_lanczos_post(ctx, kd, k + 1, w, n, n);
+            if (k + 1 < hint && k + 1 < kmax) continue;
+            FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i, kd.flag, 4 * sizeof(int),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+            if (ctx->h_pinned_i[3]) {
+                done = k + 1;
+                break;
+            }
         }
+    } catch (...) {
+        ctx->kstop = nullptr;
+        throw;
     }
-    throw Error{FTD_ENOCONV, "Krylov exponential did not converge within mmax vectors"};
+    ctx->kstop = nullptr;
+    if (!done) throw Error{FTD_ENOCONV, "Krylov exponential did not converge within mmax vectors"};
+    const int conv = ctx->h_pinned_i[0], failed = ctx->h_pinned_i[2], m = ctx->h_pinned_i[1];
+    FTD_CHECK(!failed || conv, FTD_ENOCONV,
+              m >= kmax ? "Krylov exponential did not converge within mmax vectors"
+                        : "Krylov exponential: non-finite values");
+    FTD_CHECK(m >= 1 && m <= done, FTD_EDEVICE, "Krylov exponential: inconsistent vector count");
+    // iterations m .. done-1 were enqueued after the halt and did nothing
+    if (m < done) {
+        ctx->events.resize(ev_mark[m]);
+        ctx->stats.matvecs = mv_mark[m];
+    }
+    k_lincomb(ctx, V, vs, m, kd.u, kd.nrm + 1, x, n, n);
+    ctx->krylov_hint[kind] = m;
+    ctx->stats.krylov_vectors += m;
+    ctx->stats.expm_calls += 1;
+    ctx->stats.krylov_max = std::max<int64_t>(ctx->stats.krylov_max, m);
+    return m;
 }
 
 // ============================================================= gauge moves
@@ -721,21 +754,21 @@ void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
         EnvView Lv = envL_view(ctx, i, prec), Rv = envR_view(ctx, i + 1, prec);
         const int Da = psi->Dl[i], Db = psi->Dr[i];
         auto op = [&](const double* x, double* y) { heff(ctx, prec, W, Da, Db, Lv, Rv, x, y); };
-        expm_krylov(ctx, op, psi->A[i], psi->size(i), h, tol, mmax);
+        expm_krylov(ctx, op, psi->A[i], psi->size(i), h, tol, mmax, 0);
     };
     auto bond_evolve = [&](int i, double* C, int D) {
         // bond between sites i and i+1: envL[i+1], envR[i+1]
         const MpoSite& W = H->s[i];
         EnvView Lv = envL_view(ctx, i + 1, prec), Rv = envR_view(ctx, i + 1, prec);
         auto op = [&](const double* x, double* y) { keff(ctx, prec, W.wr, W.idxI_r, D, Lv, Rv, x, y); };
-        expm_krylov(ctx, op, C, (int64_t)D * D, -h, tol, mmax);
+        expm_krylov(ctx, op, C, (int64_t)D * D, -h, tol, mmax, 1);
     };
     for (int i = 0; i < L - 1; ++i) {
         site_evolve(i);
         const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
         ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Db * Db);
         double* C = ctx->ws_tmp1.as<double>();
-        qr_chol(ctx, psi->A[i], (int64_t)Da * d * d, Db, C);
+        qr_chol(ctx, psi->A[i], (int64_t)Da * d * d, Db, C, false);
         EnvView Lv = envL_view(ctx, i, prec);
         EnvView out = env_get(ctx, ctx->envL, ctx->envL_w, ctx->envL_D, i + 1, H->s[i].wr, Db, prec);
         env_left_update(ctx, prec, H->s[i], Da, Db, Lv, psi->A[i], out);
@@ -748,7 +781,7 @@ void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
         const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
         ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Da * Da);
         double* C = ctx->ws_tmp1.as<double>();
-        lq_chol(ctx, psi->A[i], Da, (int64_t)d * d * Db, C);
+        lq_chol(ctx, psi->A[i], Da, (int64_t)d * d * Db, C, false);
         EnvView Rv = envR_view(ctx, i + 1, prec);
         EnvView out = env_get(ctx, ctx->envR, ctx->envR_w, ctx->envR_D, i, H->s[i].wl, Da, prec);
         env_right_update(ctx, prec, H->s[i], Da, Db, Rv, psi->A[i], out);
@@ -756,6 +789,8 @@ void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
         absorb_left(ctx, psi, i, C);
         site_evolve(i - 1);
     }
+    // gauge moves were enqueued without waiting: report a breakdown now
+    chol_flag_check(ctx);
 }
 
 // ============================================================ MPS algebra

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
                                                    Tout* __restrict__ C,
                                                    Tin* __restrict__ partial, const GemmParams p) {
     typedef typename AccT<Tin>::type acc_t;
+    if (p.stop && *p.stop) return;
     __shared__ Tin As[2][GBK][GBM + GPAD];
     __shared__ Tin Bs[2][GBK][GBN + GPAD];
 
@@ -207,6 +208,7 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
 template <typename Tin, typename Tout>
 __global__ void gemm_reduce_kernel(const Tin* __restrict__ partial, Tout* __restrict__ C,
                                    const GemmParams p) {
+    if (p.stop && *p.stop) return;
     const int64_t MN = (int64_t)p.M * p.N;
     const int64_t pplane = (int64_t)p.ksplit * p.nprob * MN;
     const int64_t tot = MN * p.nprob;
@@ -275,6 +277,7 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
         ks = std::max(ks, 1);
     }
     p.ksplit = ks;
+    p.stop = ctx->kstop;
     size_t esz = (prec == Prec::F64) ? sizeof(double) : sizeof(float);
     void* partial = nullptr;
     if (ks > 1) {

@@ -96,6 +96,117 @@ __global__ __launch_bounds__(1024) void chol_kernel(double* G, int n, int64_t pl
 
 // Inverse of an upper-triangular U (row-major planar) into X; each thread
 // owns one column of X and back-substitutes.
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
+
+// Cholesky factor and its inverse for small n, in LDS (one workgroup).  The
+// upper triangle of the Hermitian G (row-major n x n, planar) is packed into
+// LDS (row i starts at i*n - i*(i-1)/2); the kernel adds the optional shift
+// to the diagonal, factors G = R^H R in place (R upper, real positive
+// diagonal), writes R over G (zeros below the diagonal), inverts R in place
+// and writes R^{-1} to X.  A non-positive pivot sets *flag (sticky).
+constexpr int kCholThreads = 256;
+__device__ __forceinline__ int pk(int i, int j, int n) { return i * n - (i * (i - 1)) / 2 + (j - i); }
+
+__global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, double* X, int n,
+                                                                    int64_t plane,
+                                                                    const double* shift,
+                                                                    int* flag) {
+    extern __shared__ double lds[];
+    const int T = n * (n + 1) / 2;
+    double* Pr = lds;
+    double* Pi = lds + T;
+    __shared__ double piv;
+    const int tid = threadIdx.x;
+    const double s = shift ? shift[0] : 0.0;
+    for (int e = tid; e < n * n; e += kCholThreads) {
+        const int i = e / n, j = e - i * n;
+        if (j >= i) {
+            Pr[pk(i, j, n)] = G[e] + ((i == j) ? s : 0.0);
+            Pi[pk(i, j, n)] = (i == j) ? 0.0 : G[e + plane];
+        }
+    }
+    __syncthreads();
+    // 256 threads as 8 rows x 32 columns for the trailing updates
+    const int ty = tid >> 5, tx = tid & 31;
+    for (int k = 0; k < n; ++k) {
+        if (tid == 0) {
+            const double dk = Pr[pk(k, k, n)];
+            if (!(dk > 0.0) || !isfinite(dk)) {
+                flag[0] = 1;
+                piv = 1.0;
+            } else {
+                piv = sqrt(dk);
+            }
+            Pr[pk(k, k, n)] = piv;
+        }
+        __syncthreads();
+        const double inv = 1.0 / piv;
+        const int rk = pk(k, k, n);
+        for (int j = k + 1 + tid; j < n; j += kCholThreads) {
+            Pr[rk + (j - k)] *= inv;
+            Pi[rk + (j - k)] *= inv;
+        }
+        __syncthreads();
+        // G[i][j] -= conj(R[k][i]) R[k][j] for k < i <= j
+        for (int i = k + 1 + ty; i < n; i += 8) {
+            const double ar = Pr[rk + (i - k)], ai = -Pi[rk + (i - k)];
+            const int ri = pk(i, i, n);
+            for (int j = i + tx; j < n; j += 32) {
+                const double br = Pr[rk + (j - k)], bi = Pi[rk + (j - k)];
+                Pr[ri + (j - i)] -= ar * br - ai * bi;
+                Pi[ri + (j - i)] -= ar * bi + ai * br;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += kCholThreads) {
+        const int i = e / n, j = e - i * n;
+        G[e] = (j >= i) ? Pr[pk(i, j, n)] : 0.0;
+        G[e + plane] = (j >= i) ? Pi[pk(i, j, n)] : 0.0;
+    }
+    __syncthreads();
+    // in-place inverse, column by column: X[j][j] = 1/R[j][j],
+    // X[i][j] = -(sum_{k=i}^{j-1} X[i][k] R[k][j]) / R[j][j] for i < j, where
+    // columns < j already hold X and column j still holds R
+    for (int j = 0; j < n; ++j) {
+        const double rjj = Pr[pk(j, j, n)];
+        // one row per thread group of 4 lanes
+        const int g = tid >> 2, l = tid & 3;
+        double tr[1], ti[1];
+        for (int i0 = 0; i0 < j; i0 += kCholThreads / 4) {
+            const int i = i0 + g;
+            double sr = 0.0, si = 0.0;
+            if (i < j) {
+                for (int k = i + l; k < j; k += 4) {
+                    const double xr = Pr[pk(i, k, n)], xi = Pi[pk(i, k, n)];
+                    const double rr = Pr[pk(k, j, n)], ri = Pi[pk(k, j, n)];
+                    sr += xr * rr - xi * ri;
+                    si += xr * ri + xi * rr;
+                }
+            }
+            sr += __shfl_xor(sr, 1, 64);
+            si += __shfl_xor(si, 1, 64);
+            sr += __shfl_xor(sr, 2, 64);
+            si += __shfl_xor(si, 2, 64);
+            tr[0] = sr;
+            ti[0] = si;
+            __syncthreads();   // all reads of column j done before it is overwritten
+            if (i < j && l == 0) {
+                Pr[pk(i, j, n)] = -tr[0] / rjj;
+                Pi[pk(i, j, n)] = -ti[0] / rjj;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) Pr[pk(j, j, n)] = 1.0 / rjj;
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += kCholThreads) {
+        const int i = e / n, j = e - i * n;
+        X[e] = (j >= i) ? Pr[pk(i, j, n)] : 0.0;
+        X[e + plane] = (j >= i) ? Pi[pk(i, j, n)] : 0.0;
+    }
+}
+
 __global__ void triinv_kernel(const double* __restrict__ U, double* __restrict__ X, int n,
                               int64_t plane) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,7 +264,42 @@ static GemmParams gp(int M, int N, int K) {
 
 // Shifted CholeskyQR3.  wide == false: M is m x n (row-major), M = Q R.
 // wide == true: M is n x m (row-major), M = L Q with L = R^H.
-static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout, bool wide) {
+// Factor-and-invert of the n x n Gram matrix: LDS kernel when its packed
+// triangle fits the per-workgroup LDS, else the global-memory kernels.
+static void chol_inv(Ctx* ctx, double* G, double* Xi, int64_t n, const double* shift, int* flag) {
+    const int64_t nn = n * n;
+    const size_t bytes = sizeof(double) * (size_t)(n * (n + 1));
+    int lim = 0;
+    FTD_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    bool lds = bytes + 64 <= (size_t)lim;
+    if (lds && bytes > 48 * 1024)
+        lds = hipFuncSetAttribute((const void*)chol_inv_lds_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+              hipSuccess;
+    if (lds) {
+        chol_inv_lds_kernel<<<1, kCholThreads, bytes, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag);
+    } else {
+        chol_kernel<<<1, 1024, 0, ctx->stream>>>(G, (int)n, nn, shift, flag);
+        triinv_kernel<<<(unsigned)((n + 63) / 64), 64, 0, ctx->stream>>>(G, Xi, (int)n, nn);
+    }
+    FTD_HIP(hipGetLastError());
+}
+
+void chol_flag_check(Ctx* ctx) {
+    int* flag = ctx->iscal + 8;
+    FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->h_pinned_i[0] != 0) {
+        set_int_kernel<<<1, 1, 0, ctx->stream>>>(flag, 0);
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+        throw Error{FTD_ENOCONV, "CholeskyQR breakdown: the block is numerically rank deficient"};
+    }
+}
+
+// The breakdown flag is sticky: kernels only set it; chol_flag_check reads
+// and clears it (at once when `check`, else left to the caller).
+static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout, bool wide,
+                         bool check) {
     const int64_t nn = n * n, mn = m * n;
     ctx->ws_qr.ensure(ctx, sizeof(double) * 2 * (3 * nn + mn));
     double* G = ctx->ws_qr.as<double>();
@@ -162,7 +308,6 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
     double* Q2 = Rt + 2 * nn;
     double* shift = ctx->scal + 32;
     int* flag = ctx->iscal + 8;
-    FTD_HIP(hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
     eye_kernel<<<grid1(nn), 256, 0, ctx->stream>>>(Rout, (int)n, nn);
     for (int pass = 0; pass < 3; ++pass) {
         // Gram matrix
@@ -182,8 +327,7 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
             const double c = 11.0 * ((double)m * n + (double)n * (n + 1));
             shift_kernel<<<1, 256, 0, ctx->stream>>>(G, (int)n, c, shift);
         }
-        chol_kernel<<<1, 1024, 0, ctx->stream>>>(G, (int)n, nn, pass == 0 ? shift : nullptr, flag);
-        triinv_kernel<<<(unsigned)((n + 63) / 64), 64, 0, ctx->stream>>>(G, Xi, (int)n, nn);
+        chol_inv(ctx, G, Xi, n, pass == 0 ? shift : nullptr, flag);
         // M <- M Xi (tall) or M <- Xi^H M (wide)
         GemmParams q = gp(wide ? (int)n : (int)m, wide ? (int)m : (int)n, (int)n);
         if (!wide) {
@@ -208,10 +352,7 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
         k_copy_f64(ctx, Rt, Rout, 2 * nn);
     }
     FTD_HIP(hipGetLastError());
-    FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    FTD_HIP(hipStreamSynchronize(ctx->stream));
-    FTD_CHECK(ctx->h_pinned_i[0] == 0, FTD_ENOCONV,
-              "CholeskyQR breakdown: the block is numerically rank deficient");
+    if (check) chol_flag_check(ctx);
     if (wide) {
         // L = R^H
         k_transpose(ctx, Rout, n, n, nn, Rt, nn, 1);
@@ -219,13 +360,13 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
     }
 }
 
-void qr_chol(Ctx* ctx, double* M, int64_t m, int64_t n, double* R) {
+void qr_chol(Ctx* ctx, double* M, int64_t m, int64_t n, double* R, bool check) {
     FTD_CHECK(m >= n, FTD_EINVAL, "qr_chol: needs m >= n");
-    chol_qr_impl(ctx, M, m, n, R, false);
+    chol_qr_impl(ctx, M, m, n, R, false, check);
 }
-void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L) {
+void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L, bool check) {
     FTD_CHECK(m >= n, FTD_EINVAL, "lq_chol: needs m >= n");
-    chol_qr_impl(ctx, M, m, n, L, true);
+    chol_qr_impl(ctx, M, m, n, L, true, check);
 }
 
 // -------------------------------------------------------------- Householder
@@ -690,7 +831,6 @@ __global__ __launch_bounds__(64 * kJacobiWaves) void jacobi_sweep(
     }
     if (lane == 0 && rotated) atomicAdd(count, rotated);
 }
-__global__ void set_int_kernel(int* p, int v) { *p = v; }
 __global__ void count_kernel(const int* f, int n, int* out) {
     __shared__ double sh[16];
     double s = 0.0;

@@ -41,12 +41,16 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // ---------------------------------------------------------------- basic ops
-__global__ void copy_kernel(const double* __restrict__ s, double* __restrict__ d, int64_t n) {
+__global__ void copy_kernel(const double* __restrict__ s, double* __restrict__ d, int64_t n,
+                            const int* stop) {
+    if (stop && *stop) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         d[i] = s[i];
 }
-__global__ void convert_kernel(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+__global__ void convert_kernel(const double* __restrict__ s, float* __restrict__ d, int64_t n,
+                               const int* stop) {
+    if (stop && *stop) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         d[i] = (float)s[i];
@@ -77,12 +81,12 @@ __global__ void scale_dev_kernel(double* x, int64_t n, int64_t plane, const doub
 
 void k_copy_f64(Ctx* ctx, const double* src, double* dst, int64_t n) {
     if (n <= 0) return;
-    copy_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, dst, n);
+    copy_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, dst, n, ctx->kstop);
     FTD_HIP(hipGetLastError());
 }
 void k_convert_f64_f32(Ctx* ctx, const double* src, float* dst, int64_t n) {
     if (n <= 0) return;
-    convert_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, dst, n);
+    convert_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(src, dst, n, ctx->kstop);
     FTD_HIP(hipGetLastError());
 }
 void k_scale_cplx(Ctx* ctx, double* x, int64_t n, int64_t plane, double re, double im) {
@@ -95,9 +99,19 @@ void k_scale_by_dev(Ctx* ctx, double* x, int64_t n, int64_t plane, const double*
     scale_dev_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(x, n, plane, s, mode);
     FTD_HIP(hipGetLastError());
 }
+__global__ void zero_kernel(uint32_t* p, int64_t n, const int* stop) {
+    if (stop && *stop) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+// a fill kernel rather than a memset, so it can be predicated and captured
 void k_zero(Ctx* ctx, void* p, size_t bytes) {
     if (bytes == 0) return;
-    FTD_HIP(hipMemsetAsync(p, 0, bytes, ctx->stream));
+    FTD_CHECK(bytes % 4 == 0, FTD_EINVAL, "k_zero: size not a multiple of 4 bytes");
+    const int64_t n = (int64_t)(bytes / 4);
+    zero_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(static_cast<uint32_t*>(p), n, ctx->kstop);
+    FTD_HIP(hipGetLastError());
 }
 
 // --------------------------------------------------------------- reductions
@@ -119,7 +133,8 @@ __global__ void dot_partial(const double* __restrict__ x, const double* __restri
     }
 }
 __global__ void nrm2_partial(const double* __restrict__ x, int64_t n, int64_t plane,
-                             double* __restrict__ part) {
+                             double* __restrict__ part, const int* stop) {
+    if (stop && *stop) return;
     __shared__ double sh[16];
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -131,7 +146,9 @@ __global__ void nrm2_partial(const double* __restrict__ x, int64_t n, int64_t pl
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 // sum `cnt` groups of `nb` partials, each group `width` wide (interleaved)
-__global__ void sum_partials(const double* __restrict__ part, int nb, int width, double* out) {
+__global__ void sum_partials(const double* __restrict__ part, int nb, int width, double* out,
+                             const int* stop) {
+    if (stop && *stop) return;
     __shared__ double sh[16];
     const int g = blockIdx.x;
     for (int c = 0; c < width; ++c) {
@@ -147,22 +164,23 @@ void k_dot(Ctx* ctx, const double* x, const double* y, int64_t n, int64_t plane,
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
     dot_partial<<<nb, RB, 0, ctx->stream>>>(x, y, n, plane, part);
-    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 2, out);
+    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 2, out, nullptr);
     FTD_HIP(hipGetLastError());
 }
 void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out) {
     const int nb = red_blocks(n);
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
-    nrm2_partial<<<nb, RB, 0, ctx->stream>>>(x, n, plane, part);
-    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 1, out);
+    nrm2_partial<<<nb, RB, 0, ctx->stream>>>(x, n, plane, part, ctx->kstop);
+    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 1, out, ctx->kstop);
     FTD_HIP(hipGetLastError());
 }
 
 // h[j] = <V_j, w>: grid (nb, k)
 __global__ void multidot_partial(const double* __restrict__ V, int64_t vstride,
                                  const double* __restrict__ w, int64_t n, int64_t plane,
-                                 double* __restrict__ part) {
+                                 double* __restrict__ part, const int* stop) {
+    if (stop && *stop) return;
     __shared__ double sh[16];
     const int j = blockIdx.y;
     const double* v = V + (int64_t)j * vstride;
@@ -188,14 +206,16 @@ void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double*
     nb = std::min(nb, 128);
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
-    multidot_partial<<<dim3(nb, k), RB, 0, ctx->stream>>>(V, vstride, w, n, plane, part);
-    sum_partials<<<k, RB, 0, ctx->stream>>>(part, nb, 2, h);
+    multidot_partial<<<dim3(nb, k), RB, 0, ctx->stream>>>(V, vstride, w, n, plane, part,
+                                                          ctx->kstop);
+    sum_partials<<<k, RB, 0, ctx->stream>>>(part, nb, 2, h, ctx->kstop);
     FTD_HIP(hipGetLastError());
 }
 
 __global__ void multiaxpy_kernel(const double* __restrict__ V, int64_t vstride, int k,
                                  const double* __restrict__ h, double* __restrict__ w, int64_t n,
-                                 int64_t plane) {
+                                 int64_t plane, const int* stop) {
+    if (stop && *stop) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double ar = w[i], ai = w[i + plane];
@@ -212,7 +232,8 @@ __global__ void multiaxpy_kernel(const double* __restrict__ V, int64_t vstride, 
 void k_multiaxpy(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h, double* w,
                  int64_t n, int64_t plane) {
     if (k <= 0 || n <= 0) return;
-    multiaxpy_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane);
+    multiaxpy_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane,
+                                                           ctx->kstop);
     FTD_HIP(hipGetLastError());
 }
 
@@ -242,90 +263,93 @@ void k_lincomb(Ctx* ctx, const double* V, int64_t vstride, int k, const double* 
 }
 
 // ------------------------------------------------------------ channel mixing
-template <typename Tin, typename Tout, int MAXD>
-__global__ void chanmix_kernel(const Tin* __restrict__ in, const Tin* __restrict__ ops,
-                               Tout* __restrict__ out, const MixParams p) {
-    const int d = p.d;
+// y[a][o][q][b] (+)= sum_entries sum_p op[o][p] x[a][p][q][b] for every job
+// (output channel).  Grid: x over b (the contiguous index), y over the row
+// (a, q), z over jobs.  DN > 0 is the exact local dimension (unrolled); DN = 0
+// handles any d <= 32.
+template <typename Tin, typename Tout, int DN>
+__global__ __launch_bounds__(256) void chanmix_kernel(const Tin* __restrict__ in,
+                                                      const Tin* __restrict__ ops,
+                                                      Tout* __restrict__ out, const MixParams p) {
+    if (p.stop && *p.stop) return;
+    constexpr int MAXD = DN > 0 ? DN : 32;
+    const int d = DN > 0 ? DN : p.d;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= p.Db) return;
+    const int row = blockIdx.y;            // a * d + q
+    const int a = row / d, q = row - a * d;
+    const int job = blockIdx.z;
     const int64_t ldi = p.ldIn ? p.ldIn : p.Db;
     const int64_t ldo = p.ldOut ? p.ldOut : p.Db;
-    const int64_t per = (int64_t)p.Da * d * p.Db;
-    const int64_t tot = per * p.njobs;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int job = (int)(e / per);
-        const int64_t r = e % per;
-        const int a = (int)(r / ((int64_t)d * p.Db));
-        const int q = (int)((r / p.Db) % d);
-        const int b = (int)(r % p.Db);
-        Tin accr[MAXD], acci[MAXD];
+    Tin accr[MAXD], acci[MAXD];
 #pragma unroll
-        for (int o = 0; o < MAXD; ++o) {
-            accr[o] = 0;
-            acci[o] = 0;
-        }
-        for (int en = p.job[job].e0; en < p.job[job].e1; ++en) {
-            const Tin* x = in + p.ent[en].offIn + ((int64_t)a * d * d + q) * ldi + b;
-            const Tin* opr = ops + (int64_t)p.ent[en].op * p.opStride;
-            const Tin* opi = opr + (int64_t)d * d;
-            for (int pp = 0; pp < d; ++pp) {
-                const Tin xr = x[pp * d * ldi], xi = x[pp * d * ldi + p.planeIn];
+    for (int o = 0; o < MAXD; ++o) {
+        accr[o] = 0;
+        acci[o] = 0;
+    }
+    for (int en = p.job[job].e0; en < p.job[job].e1; ++en) {
+        const Tin* x = in + p.ent[en].offIn + ((int64_t)a * d * d + q) * ldi + b;
+        const Tin* opr = ops + (int64_t)p.ent[en].op * p.opStride;
+        const Tin* opi = opr + (int64_t)d * d;
+        for (int pp = 0; pp < d; ++pp) {
+            const Tin xr = x[(int64_t)pp * d * ldi], xi = x[(int64_t)pp * d * ldi + p.planeIn];
 #pragma unroll
-                for (int o = 0; o < MAXD; ++o) {
-                    if (o < d) {
-                        const Tin orr = opr[o * d + pp], oi = opi[o * d + pp];
-                        accr[o] += orr * xr - oi * xi;
-                        acci[o] += orr * xi + oi * xr;
-                    }
+            for (int o = 0; o < MAXD; ++o) {
+                if (DN > 0 || o < d) {
+                    const Tin orr = opr[o * d + pp], oi = opi[o * d + pp];
+                    accr[o] += orr * xr - oi * xi;
+                    acci[o] += orr * xi + oi * xr;
                 }
             }
         }
-        Tout* y = out + p.job[job].offOut + ((int64_t)a * d * d + q) * ldo + b;
+    }
+    Tout* y = out + p.job[job].offOut + ((int64_t)a * d * d + q) * ldo + b;
 #pragma unroll
-        for (int o = 0; o < MAXD; ++o) {
-            if (o < d) {
-                if (p.accumulate) {
-                    y[o * d * ldo] += (Tout)accr[o];
-                    y[o * d * ldo + p.planeOut] += (Tout)acci[o];
-                } else {
-                    y[o * d * ldo] = (Tout)accr[o];
-                    y[o * d * ldo + p.planeOut] = (Tout)acci[o];
-                }
-            }
+    for (int o = 0; o < MAXD; ++o) {
+        if (DN == 0 && o >= d) continue;
+        if (p.accumulate) {
+            y[(int64_t)o * d * ldo] += (Tout)accr[o];
+            y[(int64_t)o * d * ldo + p.planeOut] += (Tout)acci[o];
+        } else {
+            y[(int64_t)o * d * ldo] = (Tout)accr[o];
+            y[(int64_t)o * d * ldo + p.planeOut] = (Tout)acci[o];
         }
     }
 }
 
 template <typename Tin, typename Tout>
 static void chanmix_t(Ctx* ctx, const void* in, const void* ops, void* out, const MixParams& p) {
-    const int64_t tot = (int64_t)p.Da * p.d * p.Db * p.njobs;
-    if (tot <= 0) return;
-    dim3 g = grid_for(tot);
+    if ((int64_t)p.Da * p.d * p.Db * p.njobs <= 0) return;
+    const int tb = p.Db >= 256 ? 256 : (p.Db >= 128 ? 128 : 64);
+    dim3 g((p.Db + tb - 1) / tb, (unsigned)(p.Da * p.d), (unsigned)p.njobs);
     const Tin* a = static_cast<const Tin*>(in);
     const Tin* o = static_cast<const Tin*>(ops);
     Tout* y = static_cast<Tout*>(out);
-    if (p.d <= 2)
-        chanmix_kernel<Tin, Tout, 2><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
-    else if (p.d <= 4)
-        chanmix_kernel<Tin, Tout, 4><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
-    else if (p.d <= 8)
-        chanmix_kernel<Tin, Tout, 8><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
-    else if (p.d <= 16)
-        chanmix_kernel<Tin, Tout, 16><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
-    else
-        chanmix_kernel<Tin, Tout, 32><<<g, 256, 0, ctx->stream>>>(a, o, y, p);
+    switch (p.d) {
+        case 2: chanmix_kernel<Tin, Tout, 2><<<g, tb, 0, ctx->stream>>>(a, o, y, p); break;
+        case 4: chanmix_kernel<Tin, Tout, 4><<<g, tb, 0, ctx->stream>>>(a, o, y, p); break;
+        case 6: chanmix_kernel<Tin, Tout, 6><<<g, tb, 0, ctx->stream>>>(a, o, y, p); break;
+        case 8: chanmix_kernel<Tin, Tout, 8><<<g, tb, 0, ctx->stream>>>(a, o, y, p); break;
+        case 10: chanmix_kernel<Tin, Tout, 10><<<g, tb, 0, ctx->stream>>>(a, o, y, p); break;
+        case 12: chanmix_kernel<Tin, Tout, 12><<<g, tb, 0, ctx->stream>>>(a, o, y, p); break;
+        default: chanmix_kernel<Tin, Tout, 0><<<g, tb, 0, ctx->stream>>>(a, o, y, p); break;
+    }
     FTD_HIP(hipGetLastError());
 }
 
 void chanmix(Ctx* ctx, Prec prec, bool out_f64, const void* in, const void* ops, void* out,
              const MixParams& p) {
     FTD_CHECK(p.d <= 32, FTD_EINVAL, "local dimension above 32 is not supported");
+    FTD_CHECK((int64_t)p.Da * p.d < 65536, FTD_EINVAL, "channel mixer: Da * d too large");
     if (p.njobs == 0) return;
+    MixParams q = p;
+    q.stop = ctx->kstop;
     if (prec == Prec::F64)
-        chanmix_t<double, double>(ctx, in, ops, out, p);
+        chanmix_t<double, double>(ctx, in, ops, out, q);
     else if (out_f64)
-        chanmix_t<float, double>(ctx, in, ops, out, p);
+        chanmix_t<float, double>(ctx, in, ops, out, q);
     else
-        chanmix_t<float, float>(ctx, in, ops, out, p);
+        chanmix_t<float, float>(ctx, in, ops, out, q);
 }
 
 // ------------------------------------------------------ MPO x MPS, embedding
@@ -442,12 +466,19 @@ void k_transpose(Ctx* ctx, const double* src, int64_t rows, int64_t cols, int64_
 // wavefront: lane j owns row j of the eigenvector matrix; the scalar
 // recurrences are evaluated identically in every lane and exchanged by
 // lane reads).  Also records beta_{n-1} = |w| and the convergence decision.
-__device__ __forceinline__ double lane_get(double v, int i) { return __shfl(v, i, 64); }
+// Value of v in lane i, for a wavefront-uniform i: two v_readlane into scalar
+// registers (much cheaper than a cross-lane permute through LDS).
+__device__ __forceinline__ double lane_get(double v, int i) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+    return __hiloint2double(hi, lo);
+}
 
 __global__ __launch_bounds__(64) void tridiag_expm_kernel(KrylovDev kd, int n, double zr,
                                                           double zi, double tol, int exhausted,
                                                           int mmax) {
     __shared__ double Z[kMaxKrylov][kMaxKrylov + 1];
+    if (kd.flag[3]) return;   // an earlier iteration converged or failed
     const int j = threadIdx.x;
     const double bnew = sqrt(fmax(kd.nrm[0], 0.0));
     double dj = (j < n) ? kd.alpha[j] : 0.0;
@@ -529,15 +560,18 @@ __global__ __launch_bounds__(64) void tridiag_expm_kernel(KrylovDev kd, int n, d
         kd.beta[n - 1] = bnew;
         const bool finite = isfinite(nn) && isfinite(bnew);
         const int conv = (exhausted || err <= tol * sqrt(nn) || bnew == 0.0) ? 1 : 0;
-        kd.flag[0] = (finite && !fail) ? conv : 0;
+        const int ok = (finite && !fail) ? conv : 0;
+        const int bad = (!finite || fail || (!conv && n >= mmax)) ? 1 : 0;
+        kd.flag[0] = ok;
         kd.flag[1] = n;
-        kd.flag[2] = (!finite || fail || (!conv && n >= mmax)) ? 1 : 0;
+        kd.flag[2] = bad;
+        kd.flag[3] = (ok || bad) ? 1 : 0;
     }
 }
 
 // w /= beta_{n-1} unless converged
 __global__ void lanczos_post_kernel(KrylovDev kd, int n, double* w, int64_t len, int64_t plane) {
-    if (kd.flag[0] || kd.flag[2]) return;
+    if (kd.flag[3]) return;
     const double b = kd.beta[n - 1];
     const double f = 1.0 / b;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
@@ -546,7 +580,20 @@ __global__ void lanczos_post_kernel(KrylovDev kd, int n, double* w, int64_t len,
         w[i + plane] *= f;
     }
 }
-__global__ void set_alpha_kernel(KrylovDev kd, int k) { kd.alpha[k] = kd.h[2 * k]; }
+__global__ void set_alpha_kernel(KrylovDev kd, int k) {
+    if (kd.flag[3]) return;
+    kd.alpha[k] = kd.h[2 * k];
+}
+__global__ void krylov_reset_kernel(KrylovDev kd) {
+    kd.flag[0] = 0;
+    kd.flag[1] = 0;
+    kd.flag[2] = 0;
+    kd.flag[3] = 0;
+}
+void k_krylov_reset(Ctx* ctx, KrylovDev kd) {
+    krylov_reset_kernel<<<1, 1, 0, ctx->stream>>>(kd);
+    FTD_HIP(hipGetLastError());
+}
 
 void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
                     int exhausted) {
