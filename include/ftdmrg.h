@@ -200,6 +200,17 @@ ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t
 ftd_status ftd_tdvp_step(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt_real,
                          double dt_imag, const ftd_krylov_opts* ko);
 
+/* One TDVP step (as ftd_tdvp_step) of each of two different states, run
+ * concurrently: psi on the context's stream, phi on a second stream of the
+ * context (created on first use, released with the context) from a second
+ * host thread.  The states are independent; this is the per-time-step work
+ * of the current correlation (real time: both states advance by dt).  Work
+ * the caller queued before the call is visible to both; the call returns
+ * with the caller's stream ordered after both steps.  Statistics and timing
+ * cover both streams.  Errors: as ftd_tdvp_step; FTD_EINVAL if psi == phi. */
+ftd_status ftd_tdvp_pair(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, ftd_mps* phi,
+                         double dt_real, double dt_imag, const ftd_krylov_opts* ko);
+
 /* Exact MPO x MPS product followed by compression to D (s/s_max > cutoff):
  * out = compress(O psi).  Used for j|Psi_beta>.  out belongs to the caller. */
 ftd_status ftd_apply_compress(ftd_ctx* ctx, const ftd_mpo* O, const ftd_mps* psi, int32_t D,

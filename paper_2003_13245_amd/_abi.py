@@ -81,6 +81,7 @@ SIGNATURES = {
     "ftd_mps_norm": (I32, [P, P, DP]),
     "ftd_mps_set_precision": (I32, [P, I32]),
     "ftd_thermal_prep": (I32, [P, P, D, I32, I32, I32, D, I32, C.POINTER(KrylovOpts), PP, DP]),
+    "ftd_tdvp_pair": (I32, [P, P, P, P, D, D, C.POINTER(KrylovOpts)]),
     "ftd_tdvp_step": (I32, [P, P, P, D, D, C.POINTER(KrylovOpts)]),
     "ftd_apply_compress": (I32, [P, P, P, I32, D, PP]),
     "ftd_overlap": (I32, [P, P, P, P, DP]),

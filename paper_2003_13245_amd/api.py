@@ -26,7 +26,7 @@ def _mark_shutdown():
     _SHUTDOWN[0] = True
 
 
-__all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step",
+__all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_pair",
            "corr_current", "mobility", "apply_compress", "overlap", "heff_apply",
            "mps_from_host", "gemm", "FtdError"]
 
@@ -204,6 +204,13 @@ def thermal_prep(ctx, H, beta, n_imag, n_grow, D, cutoff=1e-10, precision="c128"
 def tdvp_step(ctx, H, psi, dt_real=0.0, dt_imag=0.0, tol=1e-14, mmax=40):
     ko = _abi._krylov(tol, mmax)
     check(lib.ftd_tdvp_step(ctx.h, H.h, psi.h, float(dt_real), float(dt_imag), C.byref(ko)))
+
+
+def tdvp_pair(ctx, H, psi, phi, dt_real=0.0, dt_imag=0.0, tol=1e-14, mmax=40):
+    """One TDVP step of psi and of phi, run concurrently on two streams."""
+    ko = _abi._krylov(tol, mmax)
+    check(lib.ftd_tdvp_pair(ctx.h, H.h, psi.h, phi.h, float(dt_real), float(dt_imag),
+                            C.byref(ko)))
 
 
 def apply_compress(ctx, O, psi, D, cutoff=1e-10):

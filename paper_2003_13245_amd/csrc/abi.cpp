@@ -66,6 +66,31 @@ static std::vector<double> max_bond(const Mps* psi) {
 
 using namespace ftd;
 
+// The auxiliary context of a handle: own non-blocking stream (no implicit
+// ordering against the caller's stream, which may be the null stream), plain
+// hipMalloc workspaces.
+static Ctx* aux_ctx(ftd_ctx* ctx) {
+    if (ctx->aux) return ctx->aux;
+    hipStream_t s = nullptr;
+    FTD_HIP(hipSetDevice(ctx->c.device));
+    FTD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    Ctx* a = new Ctx();
+    try {
+        ctx_init(*a, ctx->c.device, s, nullptr);
+        if (!ctx->ev_fork) FTD_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        if (!ctx->ev_join) FTD_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    } catch (...) {
+        ctx_release(*a);
+        (void)hipStreamDestroy(s);
+        delete a;
+        throw;
+    }
+    a->timing = ctx->c.timing;
+    a->verbose = ctx->c.verbose;
+    ctx->aux = a;
+    return a;
+}
+
 extern "C" {
 
 const char* ftd_last_error(void) { return g_last_error.c_str(); }
@@ -79,29 +104,10 @@ ftd_status ftd_ctx_create(int32_t device, void* hip_stream, const ftd_allocator*
         FTD_CHECK(device >= 0 && device < n, FTD_EINVAL, "device index out of range");
         FTD_HIP(hipSetDevice(device));
         ftd_ctx* h = new ftd_ctx();
-        Ctx& c = h->c;
-        c.device = device;
-        c.stream = static_cast<hipStream_t>(hip_stream);
-        if (alloc && alloc->alloc && alloc->free) {
-            c.has_alloc = true;
-            c.alloc = *alloc;
-        }
         try {
-            c.scal = static_cast<double*>(dev_alloc(&c, sizeof(double) * 4096));
-            c.iscal = static_cast<int*>(dev_alloc(&c, sizeof(int) * 64));
-            FTD_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_pinned_i), sizeof(int) * 64, hipHostMallocDefault));
-            FTD_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_pinned_d), sizeof(double) * 64, hipHostMallocDefault));
-            FTD_HIP(hipMemsetAsync(c.scal, 0, sizeof(double) * 4096, c.stream));
-            FTD_HIP(hipMemsetAsync(c.iscal, 0, sizeof(int) * 64, c.stream));
-            double* s = c.scal + 256;
-            c.kd.alpha = s;
-            c.kd.beta = s + kMaxKrylov;
-            c.kd.h = s + 2 * kMaxKrylov;
-            c.kd.u = s + 4 * kMaxKrylov + 2;
-            c.kd.nrm = s + 6 * kMaxKrylov + 4;
-            c.kd.flag = c.iscal + 32;
-            FTD_HIP(hipStreamSynchronize(c.stream));
+            ctx_init(h->c, device, static_cast<hipStream_t>(hip_stream), alloc);
         } catch (...) {
+            ctx_release(h->c);
             delete h;
             throw;
         }
@@ -111,19 +117,14 @@ ftd_status ftd_ctx_create(int32_t device, void* hip_stream, const ftd_allocator*
 
 void ftd_ctx_destroy(ftd_ctx* ctx) {
     if (!ctx) return;
-    Ctx& c = ctx->c;
-    (void)hipStreamSynchronize(c.stream);
-    for (auto* b : {&c.ws_gemm_partial, &c.ws_red, &c.ws_T, &c.ws_U, &c.ws_X32, &c.ws_Y32,
-                    &c.ws_Krylov, &c.ws_tmp1, &c.ws_tmp2, &c.ws_tmp3, &c.ws_qr, &c.ws_svd1,
-                    &c.ws_svd2, &c.ws_svd3, &c.ws_site, &c.ws_perm, &c.ws_A32})
-        b->release(&c);
-    for (auto& b : c.envL) b.release(&c);
-    for (auto& b : c.envR) b.release(&c);
-    dev_free(&c, c.scal);
-    dev_free(&c, c.iscal);
-    if (c.h_pinned_i) (void)hipHostFree(c.h_pinned_i);
-    if (c.h_pinned_d) (void)hipHostFree(c.h_pinned_d);
-    for (auto e : c.event_pool) (void)hipEventDestroy(e);
+    if (ctx->aux) {
+        ctx_release(*ctx->aux);
+        (void)hipStreamDestroy(ctx->aux->stream);
+        delete ctx->aux;
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    ctx_release(ctx->c);
     delete ctx;
 }
 
@@ -131,6 +132,7 @@ ftd_status ftd_ctx_set_timing(ftd_ctx* ctx, int32_t enable) {
     return guarded([&] {
         FTD_CHECK(ctx, FTD_EINVAL, "null context");
         ctx->c.timing = enable != 0;
+        if (ctx->aux) ctx->aux->timing = enable != 0;
     });
 }
 
@@ -138,16 +140,20 @@ ftd_status ftd_ctx_set_verbose(ftd_ctx* ctx, int32_t level) {
     return guarded([&] {
         FTD_CHECK(ctx, FTD_EINVAL, "null context");
         ctx->c.verbose = level;
+        if (ctx->aux) ctx->aux->verbose = level;
     });
 }
 
 ftd_status ftd_ctx_stats_reset(ftd_ctx* ctx) {
     return guarded([&] {
         FTD_CHECK(ctx, FTD_EINVAL, "null context");
-        FTD_HIP(hipStreamSynchronize(ctx->c.stream));
-        ctx->c.events.clear();
-        ctx->c.event_next = 0;
-        ctx->c.stats = ftd_stats{};
+        for (Ctx* c : {&ctx->c, ctx->aux}) {
+            if (!c) continue;
+            FTD_HIP(hipStreamSynchronize(c->stream));
+            c->events.clear();
+            c->event_next = 0;
+            c->stats = ftd_stats{};
+        }
     });
 }
 
@@ -156,14 +162,24 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
         FTD_CHECK(ctx && out, FTD_EINVAL, "null argument");
         Ctx& c = ctx->c;
         FTD_HIP(hipStreamSynchronize(c.stream));
+        if (ctx->aux) FTD_HIP(hipStreamSynchronize(ctx->aux->stream));
         ftd_stats s = c.stats;
+        if (ctx->aux) {
+            const ftd_stats& a = ctx->aux->stats;
+            s.matvecs += a.matvecs;
+            s.krylov_vectors += a.krylov_vectors;
+            s.expm_calls += a.expm_calls;
+            s.krylov_max = std::max(s.krylov_max, a.krylov_max);
+        }
         s.heff_launches = 0;
         s.heff_ms = 0;
         s.heff_flops = 0;
-        // per kernel identity totals
+        // per kernel identity totals, over both streams
         std::vector<double> kms(64, 0.0), kfl(64, 0.0), kby(64, 0.0);
         std::vector<int64_t> kn(64, 0);
-        for (auto& e : c.events) {
+        std::vector<EventPair> all(c.events);
+        if (ctx->aux) all.insert(all.end(), ctx->aux->events.begin(), ctx->aux->events.end());
+        for (auto& e : all) {
             float ms = 0.f;
             FTD_HIP(hipEventElapsedTime(&ms, e.a, e.b));
             if (e.tag == TAG_HEFF || e.tag == TAG_KEFF) {
@@ -464,6 +480,23 @@ ftd_status ftd_tdvp_step(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt
     });
 }
 
+ftd_status ftd_tdvp_pair(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, ftd_mps* phi,
+                         double dt_real, double dt_imag, const ftd_krylov_opts* ko) {
+    return guarded([&] {
+        FTD_CHECK(ctx && H && psi && phi, FTD_EINVAL, "null argument");
+        FTD_CHECK(psi != phi && psi->m != phi->m, FTD_EINVAL, "the two states must differ");
+        FTD_CHECK(std::isfinite(dt_real) && std::isfinite(dt_imag), FTD_EINVAL, "non-finite step");
+        double tol;
+        int mmax;
+        check_krylov(ko, tol, mmax);
+        FTD_CHECK(H->m->L == psi->m->L && H->m->L == phi->m->L, FTD_EINVAL,
+                  "MPO and MPS lengths differ");
+        Ctx* a = aux_ctx(ctx);
+        tdvp_pair(&ctx->c, a, ctx->ev_fork, ctx->ev_join, H->m, psi->m, phi->m,
+                  cplx(-dt_imag, -dt_real), tol, mmax);
+    });
+}
+
 ftd_status ftd_apply_compress(ftd_ctx* ctx, const ftd_mpo* O, const ftd_mps* psi, int32_t D,
                               double cutoff, ftd_mps** out) {
     return guarded([&] {
@@ -518,9 +551,10 @@ ftd_status ftd_corr_current(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mpo* J,
             cplx c0 = overlap(c, psi, J->m, phi);
             C_out[0] = c0.real();
             C_out[1] = c0.imag();
+            Ctx* a = n_steps > 0 ? aux_ctx(ctx) : nullptr;
             for (int k = 1; k <= n_steps; ++k) {
-                tdvp_step(c, H->m, psi, cplx(0.0, -dt), tol, mmax);
-                tdvp_step(c, H->m, phi, cplx(0.0, -dt), tol, mmax);
+                tdvp_pair(c, a, ctx->ev_fork, ctx->ev_join, H->m, psi, phi, cplx(0.0, -dt), tol,
+                          mmax);
                 cplx ck = overlap(c, psi, J->m, phi);
                 C_out[2 * k] = ck.real();
                 C_out[2 * k + 1] = ck.imag();

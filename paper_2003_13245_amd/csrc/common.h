@@ -279,6 +279,15 @@ inline void vlog(const Ctx* ctx, int level, const char* fmt, ...) {
     va_end(ap);
 }
 
+// context set-up / release (device scalars, pinned readback, workspaces)
+void ctx_init(Ctx& c, int device, hipStream_t stream, const ftd_allocator* alloc);
+void ctx_release(Ctx& c);
+// one TDVP step of a (on ca) and of b (on cb) at the same time, from two host
+// threads; cb's stream is ordered after ca's prior work and ca's stream after
+// both steps
+void tdvp_pair(Ctx* ca, Ctx* cb, hipEvent_t fork, hipEvent_t join, const Mpo* H, Mps* a, Mps* b,
+               cplx z, double tol, int mmax);
+
 hipEvent_t timing_event(Ctx* ctx);
 void record_kernel(Ctx* ctx, hipEvent_t a, hipEvent_t b, double flops, double bytes, int tag,
                    int kind, hipEvent_t mid = nullptr);
@@ -317,6 +326,10 @@ void heff_apply_host(Ctx* ctx, const Mpo* H, const Mps* psi, int site, const dou
 
 struct ftd_ctx {
     ftd::Ctx c;
+    // second context on its own stream, created on first use: the two states
+    // of the correlation loop are propagated concurrently
+    ftd::Ctx* aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 struct ftd_mpo {
     ftd::Mpo* m;

@@ -8,8 +8,10 @@
 // (real plane, then imaginary plane).  Environments hold one D x D block per
 // MPO channel, each block [re plane][im plane].
 #include <algorithm>
+#include <exception>
 #include <functional>
 #include <numeric>
+#include <thread>
 
 #include "common.h"
 
@@ -51,6 +53,51 @@ void DBuf::release(Ctx* ctx) {
     dev_free(ctx, p);
     p = nullptr;
     bytes = 0;
+}
+
+void ctx_init(Ctx& c, int device, hipStream_t stream, const ftd_allocator* alloc) {
+    c.device = device;
+    c.stream = stream;
+    if (alloc && alloc->alloc && alloc->free) {
+        c.has_alloc = true;
+        c.alloc = *alloc;
+    }
+    c.scal = static_cast<double*>(dev_alloc(&c, sizeof(double) * 4096));
+    c.iscal = static_cast<int*>(dev_alloc(&c, sizeof(int) * 64));
+    FTD_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_pinned_i), sizeof(int) * 64,
+                          hipHostMallocDefault));
+    FTD_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_pinned_d), sizeof(double) * 64,
+                          hipHostMallocDefault));
+    FTD_HIP(hipMemsetAsync(c.scal, 0, sizeof(double) * 4096, c.stream));
+    FTD_HIP(hipMemsetAsync(c.iscal, 0, sizeof(int) * 64, c.stream));
+    double* s = c.scal + 256;
+    c.kd.alpha = s;
+    c.kd.beta = s + kMaxKrylov;
+    c.kd.h = s + 2 * kMaxKrylov;
+    c.kd.u = s + 4 * kMaxKrylov + 2;
+    c.kd.nrm = s + 6 * kMaxKrylov + 4;
+    c.kd.flag = c.iscal + 32;
+    FTD_HIP(hipStreamSynchronize(c.stream));
+}
+
+void ctx_release(Ctx& c) {
+    (void)hipStreamSynchronize(c.stream);
+    for (auto* b : {&c.ws_gemm_partial, &c.ws_red, &c.ws_T, &c.ws_U, &c.ws_X32, &c.ws_Y32,
+                    &c.ws_Krylov, &c.ws_tmp1, &c.ws_tmp2, &c.ws_tmp3, &c.ws_qr, &c.ws_svd1,
+                    &c.ws_svd2, &c.ws_svd3, &c.ws_site, &c.ws_perm, &c.ws_A32})
+        b->release(&c);
+    for (auto& b : c.envL) b.release(&c);
+    for (auto& b : c.envR) b.release(&c);
+    dev_free(&c, c.scal);
+    dev_free(&c, c.iscal);
+    c.scal = nullptr;
+    c.iscal = nullptr;
+    if (c.h_pinned_i) (void)hipHostFree(c.h_pinned_i);
+    if (c.h_pinned_d) (void)hipHostFree(c.h_pinned_d);
+    c.h_pinned_i = nullptr;
+    c.h_pinned_d = nullptr;
+    for (auto e : c.event_pool) (void)hipEventDestroy(e);
+    c.event_pool.clear();
 }
 
 hipEvent_t timing_event(Ctx* ctx) {
@@ -791,6 +838,32 @@ void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
     }
     // gauge moves were enqueued without waiting: report a breakdown now
     chol_flag_check(ctx);
+}
+
+void tdvp_pair(Ctx* ca, Ctx* cb, hipEvent_t fork, hipEvent_t join, const Mpo* H, Mps* a, Mps* b,
+               cplx z, double tol, int mmax) {
+    FTD_HIP(hipEventRecord(fork, ca->stream));
+    FTD_HIP(hipStreamWaitEvent(cb->stream, fork, 0));
+    std::exception_ptr err_b;
+    std::thread worker([&] {
+        try {
+            FTD_HIP(hipSetDevice(cb->device));
+            tdvp_step(cb, H, b, z, tol, mmax);
+        } catch (...) {
+            err_b = std::current_exception();
+        }
+    });
+    std::exception_ptr err_a;
+    try {
+        tdvp_step(ca, H, a, z, tol, mmax);
+    } catch (...) {
+        err_a = std::current_exception();
+    }
+    worker.join();
+    FTD_HIP(hipEventRecord(join, cb->stream));
+    FTD_HIP(hipStreamWaitEvent(ca->stream, join, 0));
+    if (err_a) std::rethrow_exception(err_a);
+    if (err_b) std::rethrow_exception(err_b);
 }
 
 // ============================================================ MPS algebra

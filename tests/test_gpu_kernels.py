@@ -135,3 +135,29 @@ def test_pc_stage(ctx, D):
     assert got.bond_dims() == ref.bond_dims(), (got.bond_dims(), ref.bond_dims())
     dist = mps_rel_distance(got, ref)
     assert dist < 1e-11, dist
+
+
+@pytest.mark.parametrize("kind", ["real", "imag"])
+def test_tdvp_pair_matches_two_steps(ctx, kind):
+    """The concurrent pair step gives the same states as two single steps."""
+    from paper_2003_13245_amd import api
+    m = small_model(n_mol=3, n_loc=1, n_nl=1, levels=3)
+    dims = Mdl.site_dims(m)
+    H, J = api.mpo_build(ctx, m)
+    rng = np.random.default_rng(17)
+    a = random_mps(dims, 8, rng, 0)
+    b = random_mps(dims, 6, rng, 0)
+    kw = dict(dt_real=0.1) if kind == "real" else dict(dt_imag=0.05)
+    say(f"[tdvp_pair] {kind}")
+    ga, gb = api.mps_from_host(ctx, a.A), api.mps_from_host(ctx, b.A)
+    sa, sb = api.mps_from_host(ctx, a.A), api.mps_from_host(ctx, b.A)
+    for _ in range(2):
+        api.tdvp_pair(ctx, H, ga, gb, **kw)
+        api.tdvp_step(ctx, H, sa, **kw)
+        api.tdvp_step(ctx, H, sb, **kw)
+    for g, s in ((ga, sa), (gb, sb)):
+        x, y = gpu_tensors(g, dims), gpu_tensors(s, dims)
+        assert x.bond_dims() == y.bond_dims()
+        assert mps_rel_distance(x, y) < 1e-13
+    with pytest.raises(api.FtdError):
+        api.tdvp_pair(ctx, H, ga, ga, **kw)
