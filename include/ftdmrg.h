@@ -107,9 +107,11 @@ const char* ftd_last_error(void);
  * ftd_ctx_stats synchronises and returns, for the contraction kernels of the
  * H_eff / K_eff matvecs since the last reset: number of launches, summed
  * kernel milliseconds and summed algorithmic flops (8 m n k per complex
- * product); the same for the single GEMM kernel instance with the largest
- * time share (dom_*, timed without its split-K reduction); and over the
- * whole context the number of matvecs and Krylov vectors.  Statistics are reset by ftd_ctx_stats_reset. */
+ * product), each bracketed by events; the same for the single GEMM kernel
+ * instance with the largest time share (dom_*), whose launches are timed on
+ * the device (first block start to last block end, the kernel alone without
+ * its split-K reduction); and over the whole context the number of matvecs
+ * and Krylov vectors.  Statistics are reset by ftd_ctx_stats_reset. */
 typedef struct {
     int64_t heff_launches;
     double heff_ms;
@@ -242,6 +244,31 @@ ftd_status ftd_corr_current(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mpo* J,
  * Host-only.  Errors: FTD_EINVAL (n < 2, dt <= 0, beta < 0). */
 ftd_status ftd_mobility(const double* C, int32_t n, double dt, double beta, double e0,
                         double* mu_au, double* mu_cm2Vs);
+
+/* Mean free path of the carrier from C(t) (the mean-free-path passage, after
+ * the mobility-versus-coupling figure): group velocity v = sqrt(<j(0) j(0)>)
+ * / |e0| = sqrt(Re C(0)) / |e0| and relaxation time
+ * tau = (1/2) int_{-inf}^{inf} |Re C(t) / Re C(0)| dt, evaluated as the
+ * trapezoid of |Re C / Re C(0)| over [0, t_max] (Re C is even); l_mfp = v tau
+ * (bohr when C is in atomic units).  C: n interleaved complex samples on the
+ * uniform grid of step dt.  Host-only.  Errors: FTD_EINVAL (n < 2, dt <= 0,
+ * e0 == 0, Re C(0) <= 0). */
+ftd_status ftd_mean_free_path(const double* C, int32_t n, double dt, double e0, double* l_mfp,
+                              double* v, double* tau);
+
+/* Hopping-limit (V -> 0) current correlation of the Holstein ring, the
+ * Fermi-golden-rule comparator of the hopping-limit equation, in the form
+ * derived for this library's C(t) and j (the printed form is its complex
+ * conjugate without the two factors 2, which leaves the mobility unchanged):
+ *   C(t) = 2 (e0 R V)^2 exp(-sum_m 2 g_m^2 [(2 n_m + 1) - (n_m + 1) e^{-i w_m t}
+ *                                           - n_m e^{i w_m t}]),
+ * n_m the Bose occupation at beta.  t: nt times; omega, g: n_modes local-mode
+ * frequencies and couplings; C_out: 2*nt doubles (interleaved complex).
+ * Host-only.  Errors: FTD_EINVAL (non-positive frequency, beta <= 0: the
+ * occupations diverge at infinite temperature). */
+ftd_status ftd_fgr_corr(const double* t, int32_t nt, const double* omega, const double* g,
+                        int32_t n_modes, double V, double beta, double e0, double R,
+                        double* C_out);
 
 /* ------------------------------------------------- kernel-level entry points
  * Apply the one-site effective Hamiltonian of `site` to x, with the left

@@ -253,6 +253,30 @@ def mobility(C_t, dt, beta, e0=1.0):
     return mu.value, mu_cm.value
 
 
+def mean_free_path(C_t, dt, e0=1.0):
+    """(l_mfp, v, tau) from C(t) samples on a uniform grid."""
+    c = np.ascontiguousarray(np.asarray(C_t, dtype=np.complex128))
+    buf = np.empty(2 * c.size)
+    buf[0::2] = c.real
+    buf[1::2] = c.imag
+    out = [C.c_double() for _ in range(3)]
+    check(lib.ftd_mean_free_path(_abi._dptr(buf), int(c.size), float(dt), float(e0),
+                                 *[C.byref(o) for o in out]))
+    return tuple(o.value for o in out)
+
+
+def fgr_corr(t, V, omega, g, beta, e0=1.0, R=1.0):
+    """Hopping-limit current correlation at times t (complex array)."""
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+    gg = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    out = np.empty(2 * t.size)
+    check(lib.ftd_fgr_corr(_abi._dptr(t), int(t.size), _abi._dptr(om), _abi._dptr(gg),
+                           int(om.size), float(V), float(beta), float(e0), float(R),
+                           _abi._dptr(out)))
+    return out[0::2] + 1j * out[1::2]
+
+
 def mps_from_host(ctx, tensors, log_norm=0.0, precision="c128"):
     dims = []
     flat = []

@@ -3,6 +3,7 @@
 // and the current correlation.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 
@@ -153,6 +154,8 @@ ftd_status ftd_ctx_stats_reset(ftd_ctx* ctx) {
             c->events.clear();
             c->event_next = 0;
             c->stats = ftd_stats{};
+            timing_slots_reset(c);
+            FTD_HIP(hipStreamSynchronize(c->stream));
         }
     });
 }
@@ -177,9 +180,28 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
         // per kernel identity totals, over both streams
         std::vector<double> kms(64, 0.0), kfl(64, 0.0), kby(64, 0.0);
         std::vector<int64_t> kn(64, 0);
-        std::vector<EventPair> all(c.events);
-        if (ctx->aux) all.insert(all.end(), ctx->aux->events.begin(), ctx->aux->events.end());
-        for (auto& e : all) {
+        // device timestamps of the timed GEMM launches, per context
+        int rate_khz = 0;
+        FTD_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c.device));
+        std::vector<std::vector<unsigned long long>> slots;
+        std::vector<EventPair> all;
+        std::vector<int> owner;
+        for (Ctx* x : {&c, ctx->aux}) {
+            if (!x) continue;
+            std::vector<unsigned long long> h;
+            if (x->tslots && x->tslot_next > 0) {
+                h.resize(2 * (size_t)x->tslot_next);
+                FTD_HIP(hipMemcpy(h.data(), x->tslots, sizeof(unsigned long long) * h.size(),
+                                  hipMemcpyDeviceToHost));
+            }
+            slots.push_back(std::move(h));
+            for (auto& e : x->events) {
+                all.push_back(e);
+                owner.push_back((int)slots.size() - 1);
+            }
+        }
+        for (size_t ie = 0; ie < all.size(); ++ie) {
+            const EventPair& e = all[ie];
             float ms = 0.f;
             FTD_HIP(hipEventElapsedTime(&ms, e.a, e.b));
             if (e.tag == TAG_HEFF || e.tag == TAG_KEFF) {
@@ -188,9 +210,16 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
                 s.heff_flops += e.flops;
             }
             if (e.tag == TAG_HEFF) {
-                // the kernel alone: up to the event after the main launch
+                // the kernel alone: its device timestamps (first block start to
+                // last block end), else the events around the main launch
                 float kms_one = ms;
-                if (e.m) FTD_HIP(hipEventElapsedTime(&kms_one, e.a, e.m));
+                const auto& sl = slots[owner[ie]];
+                if (e.slot >= 0 && 2 * (size_t)e.slot + 1 < sl.size() &&
+                    sl[2 * e.slot + 1] >= sl[2 * e.slot] && rate_khz > 0) {
+                    kms_one = (float)((double)(sl[2 * e.slot + 1] - sl[2 * e.slot]) / rate_khz);
+                } else if (e.m) {
+                    FTD_HIP(hipEventElapsedTime(&kms_one, e.a, e.m));
+                }
                 const int k = e.kind & 63;
                 kms[k] += kms_one;
                 kfl[k] += e.flops;
@@ -586,6 +615,58 @@ ftd_status ftd_mobility(const double* C, int32_t n, double dt, double beta, doub
         const double e = 1.602176634e-19, a0 = 5.29177210903e-11, hbar = 1.054571817e-34;
         *mu_au = mu;
         *mu_cm2Vs = mu * e * a0 * a0 / hbar * 1e4;
+    });
+}
+
+ftd_status ftd_mean_free_path(const double* C, int32_t n, double dt, double e0, double* l_mfp,
+                              double* v, double* tau) {
+    return guarded([&] {
+        FTD_CHECK(C && l_mfp && v && tau, FTD_EINVAL, "null argument");
+        FTD_CHECK(n >= 2, FTD_EINVAL, "need at least two samples");
+        FTD_CHECK(dt > 0.0 && e0 != 0.0 && std::isfinite(dt), FTD_EINVAL, "bad dt or e0");
+        const double c0 = C[0];
+        FTD_CHECK(c0 > 0.0 && std::isfinite(c0), FTD_EINVAL, "Re C(0) must be positive");
+        // tau = (1/2) int_{-inf}^{inf} |Re C / Re C(0)| dt = int_0^tmax (Re C even)
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double w = (k == 0 || k == n - 1) ? 0.5 : 1.0;
+            s += w * std::fabs(C[2 * k] / c0);
+        }
+        *tau = dt * s;
+        *v = std::sqrt(c0) / std::fabs(e0);
+        *l_mfp = *v * *tau;
+    });
+}
+
+ftd_status ftd_fgr_corr(const double* t, int32_t nt, const double* omega, const double* g,
+                        int32_t n_modes, double V, double beta, double e0, double R,
+                        double* C_out) {
+    return guarded([&] {
+        FTD_CHECK(t && C_out && (n_modes == 0 || (omega && g)), FTD_EINVAL, "null argument");
+        FTD_CHECK(nt >= 0 && n_modes >= 0, FTD_EINVAL, "bad sizes");
+        // finite temperature only: the occupations diverge at beta = 0
+        FTD_CHECK(beta > 0.0 && std::isfinite(beta), FTD_EINVAL, "beta must be positive");
+        std::vector<double> nb(n_modes);
+        for (int m = 0; m < n_modes; ++m) {
+            FTD_CHECK(omega[m] > 0.0 && std::isfinite(omega[m]) && std::isfinite(g[m]), FTD_EINVAL,
+                      "mode frequencies must be positive and finite");
+            const double x = beta * omega[m];
+            nb[m] = x < 700.0 ? 1.0 / std::expm1(x) : 0.0;   // Bose occupation
+        }
+        const double pre = 2.0 * (e0 * R * V) * (e0 * R * V);
+        for (int k = 0; k < nt; ++k) {
+            // exponent sum_m 2 g^2 [(2n+1) - (n+1) e^{-i w t} - n e^{i w t}]
+            double er = 0.0, ei = 0.0;
+            for (int m = 0; m < n_modes; ++m) {
+                const double wt = omega[m] * t[k], c = std::cos(wt), sn = std::sin(wt);
+                const double g2 = 2.0 * g[m] * g[m];
+                er += g2 * ((2.0 * nb[m] + 1.0) - (2.0 * nb[m] + 1.0) * c);
+                ei += g2 * ((nb[m] + 1.0) * sn - nb[m] * sn);
+            }
+            const double mag = pre * std::exp(-er);
+            C_out[2 * k] = mag * std::cos(-ei);
+            C_out[2 * k + 1] = mag * std::sin(-ei);
+        }
     });
 }
 

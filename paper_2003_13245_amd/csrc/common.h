@@ -90,6 +90,9 @@ struct GemmParams {
     int nprob, ksplit;
     int a_kcontig, b_kcontig;
     const int* stop;   // launch is a no-op when *stop != 0 (Krylov halt), may be null
+    // timing slot {first block start, last block end} in wall-clock ticks
+    // (atomic min / max), or null
+    unsigned long long* tstamp;
     GemmProb prob[kMaxProbs];
     GemmTerm term[kMaxTerms];
 };
@@ -138,7 +141,10 @@ void k_dot(Ctx* ctx, const double* x, const double* y, int64_t n, int64_t plane,
 void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out);
 // h[j] = <V_j, w>, j < k; V_j at V + j*vstride
 void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double* w, int64_t n,
-                int64_t plane, double* h);
+                int64_t plane, double* h, double* alpha = nullptr);
+// w -= sum_j V_j h[j] and out[0] = |w|^2 in one pass
+void k_multiaxpy_nrm2(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
+                      double* w, int64_t n, int64_t plane, double* out);
 // w -= sum_j V_j h[j]
 void k_multiaxpy(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h, double* w,
                  int64_t n, int64_t plane);
@@ -232,6 +238,7 @@ struct EventPair {
     double flops, bytes;
     int tag;
     int kind;   // kernel identity for dominant-kernel attribution
+    int slot;   // device timestamp slot of the main kernel, or -1
 };
 
 struct Ctx {
@@ -245,6 +252,10 @@ struct Ctx {
     std::vector<EventPair> events;
     std::vector<hipEvent_t> event_pool;
     size_t event_next = 0;
+    // device timestamps of timed GEMM launches: 2 x u64 per slot
+    unsigned long long* tslots = nullptr;
+    int tslot_next = 0;
+    static constexpr int kTimingSlots = 65536;
     ftd_stats stats{};
     // scratch
     DBuf ws_gemm_partial, ws_red;
@@ -290,7 +301,11 @@ void tdvp_pair(Ctx* ca, Ctx* cb, hipEvent_t fork, hipEvent_t join, const Mpo* H,
 
 hipEvent_t timing_event(Ctx* ctx);
 void record_kernel(Ctx* ctx, hipEvent_t a, hipEvent_t b, double flops, double bytes, int tag,
-                   int kind, hipEvent_t mid = nullptr);
+                   int kind, hipEvent_t mid = nullptr, int slot = -1);
+// next device timestamp slot (allocated and cleared on first use), or null
+// when all are taken; timing_slots_reset clears them all
+unsigned long long* timing_slot(Ctx* ctx, int* index);
+void timing_slots_reset(Ctx* ctx);
 
 // ---------------------------------------------------------- high level ops
 Mpo* build_mpo(Ctx* ctx, const ftd_model& m, bool current);

@@ -90,6 +90,8 @@ void ctx_release(Ctx& c) {
     for (auto& b : c.envR) b.release(&c);
     dev_free(&c, c.scal);
     dev_free(&c, c.iscal);
+    dev_free(&c, c.tslots);
+    c.tslots = nullptr;
     c.scal = nullptr;
     c.iscal = nullptr;
     if (c.h_pinned_i) (void)hipHostFree(c.h_pinned_i);
@@ -109,8 +111,34 @@ hipEvent_t timing_event(Ctx* ctx) {
     return ctx->event_pool[ctx->event_next++];
 }
 void record_kernel(Ctx* ctx, hipEvent_t a, hipEvent_t b, double flops, double bytes, int tag,
-                   int kind, hipEvent_t mid) {
-    ctx->events.push_back({a, b, mid, flops, bytes, tag, kind});
+                   int kind, hipEvent_t mid, int slot) {
+    ctx->events.push_back({a, b, mid, flops, bytes, tag, kind, slot});
+}
+
+__global__ void tslot_clear_kernel(unsigned long long* s, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        s[2 * i] = ~0ull;
+        s[2 * i + 1] = 0ull;
+    }
+}
+void timing_slots_reset(Ctx* ctx) {
+    ctx->tslot_next = 0;
+    if (!ctx->tslots) return;
+    tslot_clear_kernel<<<64, 256, 0, ctx->stream>>>(ctx->tslots, Ctx::kTimingSlots);
+    FTD_HIP(hipGetLastError());
+}
+unsigned long long* timing_slot(Ctx* ctx, int* index) {
+    if (!ctx->tslots) {
+        ctx->tslots = static_cast<unsigned long long*>(
+            dev_alloc(ctx, sizeof(unsigned long long) * 2 * Ctx::kTimingSlots));
+        timing_slots_reset(ctx);
+    }
+    if (ctx->tslot_next >= Ctx::kTimingSlots) {
+        *index = -1;
+        return nullptr;
+    }
+    *index = ctx->tslot_next++;
+    return ctx->tslots + 2 * (size_t)*index;
 }
 
 // ============================================================ small kernels
@@ -664,12 +692,10 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
             double* vk = V + (int64_t)k * vs;
             double* w = V + (int64_t)(k + 1) * vs;
             op(vk, w);
-            k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
-            k_set_alpha(ctx, kd, k);
+            k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h, kd.alpha + k);   // alpha_k = <v_k, w>
             k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
             k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
-            k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
-            k_nrm2(ctx, w, n, n, kd.nrm);
+            k_multiaxpy_nrm2(ctx, V, vs, k + 1, kd.h, w, n, n, kd.nrm);
             const int exhausted = (k + 1 == n) ? 1 : 0;
             k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted);
             k_lanczos_post(ctx, kd, k + 1, w, n, n);

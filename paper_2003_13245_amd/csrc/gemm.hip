@@ -49,6 +49,7 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
                                                    Tin* __restrict__ partial, const GemmParams p) {
     typedef typename AccT<Tin>::type acc_t;
     if (p.stop && *p.stop) return;
+    if (p.tstamp && threadIdx.x == 0) atomicMin(p.tstamp, (unsigned long long)wall_clock64());
     __shared__ Tin As[2][GBK][GBM + GPAD];
     __shared__ Tin Bs[2][GBK][GBN + GPAD];
 
@@ -203,6 +204,10 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
                     }
                 }
             }
+    if (p.tstamp) {
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(p.tstamp + 1, (unsigned long long)wall_clock64());
+    }
 }
 
 template <typename Tin, typename Tout>
@@ -287,9 +292,12 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
     }
     dim3 grid(tn, tm, p.nprob * ks);
     hipEvent_t e0 = nullptr, e1 = nullptr, em = nullptr;
+    int slot = -1;
+    p.tstamp = nullptr;
     if (ctx->timing && tag != TAG_NONE) {
         e0 = timing_event(ctx);
         em = timing_event(ctx);
+        p.tstamp = timing_slot(ctx, &slot);
         FTD_HIP(hipEventRecord(e0, ctx->stream));
     }
     if (prec == Prec::F64) {
@@ -313,7 +321,7 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
                              (double)p.nprob * p.M * p.N * osz * (p.accumulate ? 2.0 : 1.0);
         // kernel identity: precision x operand layout
         const int kind = (int)prec * 8 + (out_f64 ? 4 : 0) + p.a_kcontig * 2 + p.b_kcontig;
-        record_kernel(ctx, e0, e1, flops, bytes, tag, kind, em);
+        record_kernel(ctx, e0, e1, flops, bytes, tag, kind, em, slot);
     }
 }
 

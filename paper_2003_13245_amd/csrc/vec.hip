@@ -146,8 +146,10 @@ __global__ void nrm2_partial(const double* __restrict__ x, int64_t n, int64_t pl
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 // sum `cnt` groups of `nb` partials, each group `width` wide (interleaved)
+// out[g][c] = sum_i part[g][i][c]; with `alpha`, group `ga`'s first component
+// is also stored to *alpha (the Lanczos diagonal element).
 __global__ void sum_partials(const double* __restrict__ part, int nb, int width, double* out,
-                             const int* stop) {
+                             const int* stop, double* alpha = nullptr, int ga = -1) {
     if (stop && *stop) return;
     __shared__ double sh[16];
     const int g = blockIdx.x;
@@ -155,7 +157,10 @@ __global__ void sum_partials(const double* __restrict__ part, int nb, int width,
         double s = 0.0;
         for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[((int64_t)g * nb + i) * width + c];
         s = block_sum(s, sh);
-        if (threadIdx.x == 0) out[g * width + c] = s;
+        if (threadIdx.x == 0) {
+            out[g * width + c] = s;
+            if (alpha && g == ga && c == 0) alpha[0] = s;
+        }
     }
 }
 
@@ -200,7 +205,7 @@ __global__ void multidot_partial(const double* __restrict__ V, int64_t vstride,
     }
 }
 void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double* w, int64_t n,
-                int64_t plane, double* h) {
+                int64_t plane, double* h, double* alpha) {
     if (k <= 0) return;
     int nb = red_blocks(n);
     nb = std::min(nb, 128);
@@ -208,7 +213,42 @@ void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double*
     double* part = ctx->ws_red.as<double>();
     multidot_partial<<<dim3(nb, k), RB, 0, ctx->stream>>>(V, vstride, w, n, plane, part,
                                                           ctx->kstop);
-    sum_partials<<<k, RB, 0, ctx->stream>>>(part, nb, 2, h, ctx->kstop);
+    sum_partials<<<k, RB, 0, ctx->stream>>>(part, nb, 2, h, ctx->kstop, alpha, k - 1);
+    FTD_HIP(hipGetLastError());
+}
+
+// w -= sum_j V_j h[j], then block partials of |w|^2 (one pass over w)
+__global__ void multiaxpy_nrm_partial(const double* __restrict__ V, int64_t vstride, int k,
+                                      const double* __restrict__ h, double* __restrict__ w,
+                                      int64_t n, int64_t plane, double* __restrict__ part,
+                                      const int* stop) {
+    if (stop && *stop) return;
+    __shared__ double sh[16];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double ar = w[i], ai = w[i + plane];
+        for (int j = 0; j < k; ++j) {
+            const double hr = h[2 * j], hi = h[2 * j + 1];
+            const double vr = V[(int64_t)j * vstride + i], vi = V[(int64_t)j * vstride + i + plane];
+            ar -= vr * hr - vi * hi;
+            ai -= vr * hi + vi * hr;
+        }
+        w[i] = ar;
+        w[i + plane] = ai;
+        s += ar * ar + ai * ai;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+void k_multiaxpy_nrm2(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
+                      double* w, int64_t n, int64_t plane, double* out) {
+    const int nb = red_blocks(n);
+    ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
+    double* part = ctx->ws_red.as<double>();
+    multiaxpy_nrm_partial<<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
+                                                      ctx->kstop);
+    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 1, out, ctx->kstop);
     FTD_HIP(hipGetLastError());
 }
 

@@ -80,3 +80,44 @@ def test_context_without_device_reports_error(abi):
     assert rc in (abi.FTD_EDEVICE, abi.FTD_EINVAL)
     assert not h.value
     assert abi.lib.ftd_last_error()
+
+
+def test_mean_free_path_matches_oracle(abi):
+    from oracle import analysis as An
+    from paper_2003_13245_amd import api
+    rng = np.random.default_rng(11)
+    t = np.arange(301) * 0.05
+    C = 2.5 * np.exp(-t / 3.0) * np.cos(0.7 * t) + 0.1j * np.sin(t) + 1e-3 * rng.standard_normal(t.size)
+    ref = An.mean_free_path(C, 0.05)
+    got = api.mean_free_path(C, 0.05)
+    for a, b in zip(got, ref):
+        assert abs(a - b) <= 1e-13 * abs(b)
+    # e0 scales the velocity (j carries the charge)
+    got2 = api.mean_free_path(C, 0.05, e0=2.0)
+    assert abs(got2[1] - ref[1] / 2) < 1e-14 and abs(got2[2] - ref[2]) < 1e-13
+    with pytest.raises(abi.FtdError):
+        api.mean_free_path(-np.ones(4), 0.05)
+
+
+@pytest.mark.parametrize("beta", [0.7, 40.0, 5000.0])
+def test_fgr_corr_matches_oracle(abi, beta):
+    from oracle import analysis as An
+    from paper_2003_13245_amd import api
+    t = np.linspace(0.0, 30.0, 257)
+    om, g = [0.3, 1.1, 2.4], [0.8, 0.5, 0.2]
+    ref = An.fgr_corr(t, 0.01, om, g, beta, e0=1.3, R=2.0)
+    got = api.fgr_corr(t, 0.01, om, g, beta, e0=1.3, R=2.0)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # t = 0: the exponent vanishes, C(0) = 2 (e0 R V)^2
+    assert abs(got[0] - 2 * (1.3 * 2.0 * 0.01) ** 2) < 1e-16
+    # no modes: constant
+    flat = api.fgr_corr(t, 0.01, [], [], beta)
+    assert np.allclose(flat, 2e-4, rtol=0, atol=1e-18)
+
+
+def test_fgr_corr_rejects_bad_modes(abi):
+    from paper_2003_13245_amd import api
+    with pytest.raises(abi.FtdError):
+        api.fgr_corr(np.zeros(3), 0.1, [0.0], [1.0], 1.0)
+    with pytest.raises(abi.FtdError):
+        api.fgr_corr(np.zeros(3), 0.1, [1.0], [1.0], 0.0)
