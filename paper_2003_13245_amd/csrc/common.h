@@ -275,7 +275,8 @@ struct Ctx {
     // kernels of one Lanczos iteration return at once when it is set, so
     // iterations can be queued ahead of the convergence test.
     const int* kstop = nullptr;
-    int krylov_hint[2] = {4, 4};   // recent vector counts (site, bond)
+    // vector counts of the previous exponential at each site / bond
+    std::vector<int> khint_site, khint_bond;
 };
 
 // Progress line on stderr when the context's verbose level is >= level.

@@ -666,10 +666,10 @@ static void env_right_update(Ctx* ctx, Prec prec, const MpoSite& W, int Da, int 
 // tridiagonal exponential.  Iterations are enqueued without waiting; every
 // kernel of an iteration returns at once after the device has raised the halt
 // flag, so the host reads the flags only from the expected vector count on
-// (hint: the count of the previous call of the same kind).  Timing events and
+// (hint: the count of the previous call at the same site or bond).  Timing events and
 // matvec counts of iterations that ran as no-ops are discarded.
 static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*)>& op, double* x,
-                       int64_t n, cplx z, double tol, int mmax, int kind) {
+                       int64_t n, cplx z, double tol, int mmax, int& last) {
     FTD_CHECK(mmax >= 1 && mmax < kMaxKrylov, FTD_EINVAL, "Krylov mmax out of range");
     const int64_t vs = 2 * n;
     ctx->ws_Krylov.ensure(ctx, sizeof(double) * (size_t)vs * (mmax + 1));
@@ -680,7 +680,7 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
     k_copy_f64(ctx, x, V, vs);
     k_scale_by_dev(ctx, V, n, n, kd.nrm + 1, 0);
     const int kmax = (int)std::min<int64_t>(mmax, n);
-    const int hint = std::max(1, ctx->krylov_hint[kind] - 1);
+    const int hint = std::max(1, last - 1);
     std::vector<size_t> ev_mark(kmax + 1);
     std::vector<int64_t> mv_mark(kmax + 1);
     ctx->kstop = kd.flag + 3;
@@ -725,7 +725,7 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
         ctx->stats.matvecs = mv_mark[m];
     }
     k_lincomb(ctx, V, vs, m, kd.u, kd.nrm + 1, x, n, n);
-    ctx->krylov_hint[kind] = m;
+    last = m;
     ctx->stats.krylov_vectors += m;
     ctx->stats.expm_calls += 1;
     ctx->stats.krylov_max = std::max<int64_t>(ctx->stats.krylov_max, m);
@@ -822,19 +822,21 @@ void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
     boundary_env(ctx, b, prec);
     const cplx h = 0.5 * z;
     ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * 1024 * 1024);
+    if ((int)ctx->khint_site.size() != L) ctx->khint_site.assign(L, 4);
+    if ((int)ctx->khint_bond.size() != L) ctx->khint_bond.assign(L, 4);
     auto site_evolve = [&](int i) {
         const MpoSite& W = H->s[i];
         EnvView Lv = envL_view(ctx, i, prec), Rv = envR_view(ctx, i + 1, prec);
         const int Da = psi->Dl[i], Db = psi->Dr[i];
         auto op = [&](const double* x, double* y) { heff(ctx, prec, W, Da, Db, Lv, Rv, x, y); };
-        expm_krylov(ctx, op, psi->A[i], psi->size(i), h, tol, mmax, 0);
+        expm_krylov(ctx, op, psi->A[i], psi->size(i), h, tol, mmax, ctx->khint_site[i]);
     };
     auto bond_evolve = [&](int i, double* C, int D) {
         // bond between sites i and i+1: envL[i+1], envR[i+1]
         const MpoSite& W = H->s[i];
         EnvView Lv = envL_view(ctx, i + 1, prec), Rv = envR_view(ctx, i + 1, prec);
         auto op = [&](const double* x, double* y) { keff(ctx, prec, W.wr, W.idxI_r, D, Lv, Rv, x, y); };
-        expm_krylov(ctx, op, C, (int64_t)D * D, -h, tol, mmax, 1);
+        expm_krylov(ctx, op, C, (int64_t)D * D, -h, tol, mmax, ctx->khint_bond[i]);
     };
     for (int i = 0; i < L - 1; ++i) {
         site_evolve(i);

@@ -116,8 +116,43 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, d
     double* Pr = lds;
     double* Pi = lds + T;
     __shared__ double piv;
+    __shared__ double red[kCholThreads / 64];
     const int tid = threadIdx.x;
     const double s = shift ? shift[0] : 0.0;
+    if (!shift) {
+        // G = I + E (the later CholeskyQR passes): the factor R = I + S, S =
+        // strict upper part of E plus half its diagonal, and R^{-1} = I - S
+        // are exact up to S^H S and S^2, whose entries are below n max|E|^2;
+        // taken when that bound is under 1e-17 (below rounding)
+        double mx = 0.0;
+        for (int e = tid; e < n * n; e += kCholThreads) {
+            const int i = e / n, j = e - i * n;
+            const double er = G[e] - ((i == j) ? 1.0 : 0.0), ei = G[e + plane];
+            mx = fmax(mx, fmax(fabs(er), fabs(ei)));
+        }
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if ((tid & 63) == 0) red[tid >> 6] = mx;
+        __syncthreads();
+        double m = 0.0;
+        for (int w = 0; w < kCholThreads / 64; ++w) m = fmax(m, red[w]);
+        if ((double)n * m * m <= 1e-17) {
+            for (int e = tid; e < n * n; e += kCholThreads) {
+                const int i = e / n, j = e - i * n;
+                double sr = 0.0, si = 0.0;
+                if (j > i) {
+                    sr = G[e];
+                    si = G[e + plane];
+                } else if (j == i) {
+                    sr = 0.5 * (G[e] - 1.0);
+                }
+                G[e] = ((i == j) ? 1.0 : 0.0) + sr;
+                G[e + plane] = si;
+                X[e] = ((i == j) ? 1.0 : 0.0) - sr;
+                X[e + plane] = -si;
+            }
+            return;
+        }
+    }
     for (int e = tid; e < n * n; e += kCholThreads) {
         const int i = e / n, j = e - i * n;
         if (j >= i) {
