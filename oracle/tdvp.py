@@ -148,6 +148,13 @@ def to_dense(psi):
 # --------------------------------------------------------------------------
 
 
+# Relative size of a random perturbation applied to every QR / LQ factor Q
+# (0: none).  Off in every computation; the tests set it to measure how far
+# rounding-level differences in the gauge moves alone move C(t).
+QR_NOISE = 0.0
+_qr_noise_rng = np.random.default_rng(7)
+
+
 def qr_pos(M):
     """Reduced QR with a real non-negative diagonal of R."""
     Q, R = np.linalg.qr(M, mode="reduced")
@@ -157,6 +164,9 @@ def qr_pos(M):
     ph[nz] = d[nz] / np.abs(d[nz])
     Q = Q * ph[None, :]
     R = np.conj(ph)[:, None] * R
+    if QR_NOISE:
+        Q = Q * (1 + QR_NOISE * (_qr_noise_rng.standard_normal(Q.shape)
+                                 + 1j * _qr_noise_rng.standard_normal(Q.shape)))
     return Q, R
 
 

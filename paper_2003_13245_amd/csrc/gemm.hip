@@ -1,6 +1,8 @@
 // Complex split-plane GEMM on CDNA4 matrix cores.
 //
-// One workgroup (4 wavefronts) computes a 64x64 tile of C.  Each wavefront
+// One workgroup (4 wavefronts) computes a 64x64 tile of C.  The k loop is
+// software-pipelined: the next 16-deep tile is loaded into registers while
+// the current one (in one of two LDS buffers) feeds the MFMAs.  Each wavefront
 // owns a 32x32 quadrant as 2x2 blocks of 16x16 MFMA outputs; every k-step of
 // 4 issues four real products per block (re*re, im*im, re*im, im*re) into
 // three accumulators, so Re C = RR - II and Im C = RI + IR.  Operands are
@@ -50,8 +52,9 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
     typedef typename AccT<Tin>::type acc_t;
     if (p.stop && *p.stop) return;
     if (p.tstamp && threadIdx.x == 0) atomicMin(p.tstamp, (unsigned long long)wall_clock64());
-    __shared__ Tin As[2][GBK][GBM + GPAD];
-    __shared__ Tin Bs[2][GBK][GBN + GPAD];
+    // two LDS buffers (double buffering), each [plane][k][m] / [plane][k][n]
+    __shared__ Tin As[2][2][GBK][GBM + GPAD];
+    __shared__ Tin Bs[2][2][GBK][GBN + GPAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -79,74 +82,66 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
     const Tin sa = p.conjA ? Tin(-1) : Tin(1);
     const Tin sb = p.conjB ? Tin(-1) : Tin(1);
 
-    for (int g = g0; g < g1; ++g) {
+    // this thread's share of one k-tile: 4 (re, im) pairs of A and of B
+    Tin ra[4], ia[4], rb[4], ib[4];
+    auto fetch = [&](int g) {
         const int t = t0 + g / ktiles;
         const int k0 = (g % ktiles) * GBK;
         const Tin* Ab = A + p.term[t].offA;
         const Tin* Bb = B + p.term[t].offB;
-        if (AK) {
-            const int kk = tid & 15;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int mm = (tid >> 4) + 16 * i;
-                const int gm = m0 + mm, gk = k0 + kk;
-                Tin re = 0, im = 0;
-                if (gm < p.M && gk < p.K) {
-                    const int64_t idx = (int64_t)gm * p.sAm + (int64_t)gk * p.sAk;
-                    re = Ab[idx];
-                    im = Ab[idx + p.planeA];
-                }
-                As[0][kk][mm] = re;
-                As[1][kk][mm] = sa * im;
-            }
-        } else {
-            const int mm = tid & 63;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int kk = (tid >> 6) + 4 * i;
-                const int gm = m0 + mm, gk = k0 + kk;
-                Tin re = 0, im = 0;
-                if (gm < p.M && gk < p.K) {
-                    const int64_t idx = (int64_t)gm * p.sAm + (int64_t)gk * p.sAk;
-                    re = Ab[idx];
-                    im = Ab[idx + p.planeA];
-                }
-                As[0][kk][mm] = re;
-                As[1][kk][mm] = sa * im;
+        for (int i = 0; i < 4; ++i) {
+            const int mm = AK ? (tid >> 4) + 16 * i : (tid & 63);
+            const int kk = AK ? (tid & 15) : (tid >> 6) + 4 * i;
+            const int gm = m0 + mm, gk = k0 + kk;
+            ra[i] = 0;
+            ia[i] = 0;
+            if (gm < p.M && gk < p.K) {
+                const int64_t idx = (int64_t)gm * p.sAm + (int64_t)gk * p.sAk;
+                ra[i] = Ab[idx];
+                ia[i] = sa * Ab[idx + p.planeA];
             }
         }
-        if (BKC) {
-            const int kk = tid & 15;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int nn = (tid >> 4) + 16 * i;
-                const int gn = n0 + nn, gk = k0 + kk;
-                Tin re = 0, im = 0;
-                if (gn < p.N && gk < p.K) {
-                    const int64_t idx = (int64_t)gk * p.sBk + (int64_t)gn * p.sBn;
-                    re = Bb[idx];
-                    im = Bb[idx + p.planeB];
-                }
-                Bs[0][kk][nn] = re;
-                Bs[1][kk][nn] = sb * im;
-            }
-        } else {
-            const int nn = tid & 63;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int kk = (tid >> 6) + 4 * i;
-                const int gn = n0 + nn, gk = k0 + kk;
-                Tin re = 0, im = 0;
-                if (gn < p.N && gk < p.K) {
-                    const int64_t idx = (int64_t)gk * p.sBk + (int64_t)gn * p.sBn;
-                    re = Bb[idx];
-                    im = Bb[idx + p.planeB];
-                }
-                Bs[0][kk][nn] = re;
-                Bs[1][kk][nn] = sb * im;
+        for (int i = 0; i < 4; ++i) {
+            const int nn = BKC ? (tid >> 4) + 16 * i : (tid & 63);
+            const int kk = BKC ? (tid & 15) : (tid >> 6) + 4 * i;
+            const int gn = n0 + nn, gk = k0 + kk;
+            rb[i] = 0;
+            ib[i] = 0;
+            if (gn < p.N && gk < p.K) {
+                const int64_t idx = (int64_t)gk * p.sBk + (int64_t)gn * p.sBn;
+                rb[i] = Bb[idx];
+                ib[i] = sb * Bb[idx + p.planeB];
             }
         }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int mm = AK ? (tid >> 4) + 16 * i : (tid & 63);
+            const int kk = AK ? (tid & 15) : (tid >> 6) + 4 * i;
+            As[buf][0][kk][mm] = ra[i];
+            As[buf][1][kk][mm] = ia[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int nn = BKC ? (tid >> 4) + 16 * i : (tid & 63);
+            const int kk = BKC ? (tid & 15) : (tid >> 6) + 4 * i;
+            Bs[buf][0][kk][nn] = rb[i];
+            Bs[buf][1][kk][nn] = ib[i];
+        }
+    };
+
+    if (g0 < g1) {
+        fetch(g0);
+        stash(0);
         __syncthreads();
+    }
+    for (int g = g0; g < g1; ++g) {
+        const int cur = (g - g0) & 1;
+        // the next tile's global loads are in flight during the MFMAs below
+        if (g + 1 < g1) fetch(g + 1);
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 4) {
             const int kr = kk + (lane >> 4);
@@ -154,13 +149,13 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
             Tin ar[2], ai[2], br[2], bi[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                ar[i] = As[0][kr][wm * 32 + i * 16 + c];
-                ai[i] = As[1][kr][wm * 32 + i * 16 + c];
+                ar[i] = As[cur][0][kr][wm * 32 + i * 16 + c];
+                ai[i] = As[cur][1][kr][wm * 32 + i * 16 + c];
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                br[j] = Bs[0][kr][wn * 32 + j * 16 + c];
-                bi[j] = Bs[1][kr][wn * 32 + j * 16 + c];
+                br[j] = Bs[cur][0][kr][wn * 32 + j * 16 + c];
+                bi[j] = Bs[cur][1][kr][wn * 32 + j * 16 + c];
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -172,6 +167,9 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
                     IM[i][j] = mfma4(ai[i], br[j], IM[i][j]);
                 }
         }
+        // the other buffer was last read in the previous iteration, which
+        // ended with a barrier
+        if (g + 1 < g1) stash(cur ^ 1);
         __syncthreads();
     }
 

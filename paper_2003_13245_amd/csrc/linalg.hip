@@ -110,7 +110,9 @@ __device__ __forceinline__ int pk(int i, int j, int n) { return i * n - (i * (i 
 __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, double* X, int n,
                                                                     int64_t plane,
                                                                     const double* shift,
-                                                                    int* flag) {
+                                                                    int* flag, const int* stop,
+                                                                    int* converged) {
+    if (stop && *stop) return;
     extern __shared__ double lds[];
     const int T = n * (n + 1) / 2;
     double* Pr = lds;
@@ -136,6 +138,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, d
         double m = 0.0;
         for (int w = 0; w < kCholThreads / 64; ++w) m = fmax(m, red[w]);
         if ((double)n * m * m <= 1e-17) {
+            // Q was already orthonormal to 1e-9: the next pass could only move
+            // it at the rounding level
+            if (converged && tid == 0 && m <= 1e-9) converged[0] = 1;
             for (int e = tid; e < n * n; e += kCholThreads) {
                 const int i = e / n, j = e - i * n;
                 double sr = 0.0, si = 0.0;
@@ -301,19 +306,25 @@ static GemmParams gp(int M, int N, int K) {
 // wide == true: M is n x m (row-major), M = L Q with L = R^H.
 // Factor-and-invert of the n x n Gram matrix: LDS kernel when its packed
 // triangle fits the per-workgroup LDS, else the global-memory kernels.
-static void chol_inv(Ctx* ctx, double* G, double* Xi, int64_t n, const double* shift, int* flag) {
-    const int64_t nn = n * n;
-    const size_t bytes = sizeof(double) * (size_t)(n * (n + 1));
+static bool chol_lds_fits(Ctx* ctx, int64_t n) {
     int lim = 0;
     FTD_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-    bool lds = bytes + 64 <= (size_t)lim;
+    return sizeof(double) * (size_t)(n * (n + 1)) + 64 <= (size_t)lim;
+}
+static void chol_inv(Ctx* ctx, double* G, double* Xi, int64_t n, const double* shift, int* flag,
+                     int* converged) {
+    const int64_t nn = n * n;
+    const size_t bytes = sizeof(double) * (size_t)(n * (n + 1));
+    bool lds = chol_lds_fits(ctx, n);
     if (lds && bytes > 48 * 1024)
         lds = hipFuncSetAttribute((const void*)chol_inv_lds_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
               hipSuccess;
     if (lds) {
-        chol_inv_lds_kernel<<<1, kCholThreads, bytes, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag);
+        chol_inv_lds_kernel<<<1, kCholThreads, bytes, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag,
+                                                                     ctx->kstop, converged);
     } else {
+        FTD_CHECK(ctx->kstop == nullptr, FTD_EINVAL, "chol_inv: predication needs the LDS path");
         chol_kernel<<<1, 1024, 0, ctx->stream>>>(G, (int)n, nn, shift, flag);
         triinv_kernel<<<(unsigned)((n + 63) / 64), 64, 0, ctx->stream>>>(G, Xi, (int)n, nn);
     }
@@ -343,8 +354,15 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
     double* Q2 = Rt + 2 * nn;
     double* shift = ctx->scal + 32;
     int* flag = ctx->iscal + 8;
+    // set by the second pass when the third would change Q only at rounding
+    int* converged = ctx->iscal + 10;
+    const bool lds_path = chol_lds_fits(ctx, n);
+    set_int_kernel<<<1, 1, 0, ctx->stream>>>(converged, 0);
     eye_kernel<<<grid1(nn), 256, 0, ctx->stream>>>(Rout, (int)n, nn);
     for (int pass = 0; pass < 3; ++pass) {
+        // the third pass is predicated on the second pass's verdict
+        const int* saved_stop = ctx->kstop;
+        if (pass == 2 && lds_path) ctx->kstop = converged;
         // Gram matrix
         GemmParams p = gp((int)n, (int)n, (int)m);
         if (!wide) {
@@ -362,7 +380,8 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
             const double c = 11.0 * ((double)m * n + (double)n * (n + 1));
             shift_kernel<<<1, 256, 0, ctx->stream>>>(G, (int)n, c, shift);
         }
-        chol_inv(ctx, G, Xi, n, pass == 0 ? shift : nullptr, flag);
+        chol_inv(ctx, G, Xi, n, pass == 0 ? shift : nullptr, flag,
+                 pass == 1 && lds_path ? converged : nullptr);
         // M <- M Xi (tall) or M <- Xi^H M (wide)
         GemmParams q = gp(wide ? (int)n : (int)m, wide ? (int)m : (int)n, (int)n);
         if (!wide) {
@@ -385,6 +404,7 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
         r.sCm = n; r.sCn = 1; r.planeC = nn;
         gemm(ctx, Prec::F64, true, G, Rout, Rt, r, TAG_NONE);
         k_copy_f64(ctx, Rt, Rout, 2 * nn);
+        ctx->kstop = saved_stop;
     }
     FTD_HIP(hipGetLastError());
     if (check) chol_flag_check(ctx);

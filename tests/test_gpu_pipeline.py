@@ -21,7 +21,14 @@ pipeline difference is therefore reported and held only to a loose bound:
 relative on the tiny ring), and at least 1e-3 relative.
 
 Floors per step k are running maxima of |C' - C| / |C(0)| over the oracle
-variants (relative 1e-15 perturbation of the state; the other SVD driver).
+variants: a relative 1e-15 perturbation of the state; the other SVD driver;
+and every gauge QR factor perturbed by a relative delta, where delta is the
+measured distance between one GPU step and one oracle step from the same
+state (itself held below 1e-12).  The last variant is how the oracle itself
+amplifies differences of the size by which the two implementations differ
+per step (FP64 MFMA accumulation order, CholeskyQR against Householder QR,
+the Krylov stop test); several steps of these chains contain bursts that
+amplify them a hundredfold in one step.
 The GPU must satisfy err(k) <= max(1e-10, 30 x floor(k)) at every step."""
 import numpy as np
 import pytest
@@ -89,12 +96,32 @@ class Case:
         self.C_v = self.corr(self.psi_v, "gesvd")
         self.mu = An.mobility(self.C, self.r.dt, self.r.beta)[0]
         self.mu_spread = abs(An.mobility(self.C_v, self.r.dt, self.r.beta)[0] - self.mu)
-        # floor of the dynamics from a common state
-        fl = np.maximum(np.abs(self.corr(perturbed(self.psi, 1)) - self.C),
-                        np.abs(self.corr(self.psi, "gesvd") - self.C))
+        # floor of the dynamics from a common state: the state perturbed and
+        # the other SVD driver; the per-step variant is added by set_step_noise
         self.c0 = abs(self.C[0])
-        self.floor = np.maximum.accumulate(fl / self.c0)
+        self.base = np.maximum(np.abs(self.corr(perturbed(self.psi, 1)) - self.C),
+                               np.abs(self.corr(self.psi, "gesvd") - self.C)) / self.c0
+        self.noise = None
+        self.set_floor(self.base)
+
+    def set_floor(self, fl):
+        self.floor = np.maximum.accumulate(fl)
         self.bound = np.maximum(1e-10, 30 * self.floor)
+
+    def set_step_noise(self, delta):
+        """Add the oracle's response to every gauge QR factor perturbed by a
+        relative `delta` (the measured one-step GPU/oracle difference, at
+        least 1e-15) to the floor."""
+        noise = max(1e-15, float(delta))
+        if self.noise == noise:
+            return
+        T.QR_NOISE = noise
+        try:
+            C_q = self.corr(self.psi)
+        finally:
+            T.QR_NOISE = 0.0
+        self.noise = noise
+        self.set_floor(np.maximum(self.base, np.abs(C_q - self.C) / self.c0))
 
     def prep(self, driver):
         T.SVD_DRIVER = driver
@@ -136,6 +163,22 @@ def case(name):
     return _CACHE[name]
 
 
+def one_step_difference(ctx, c):
+    """Relative distance between one real-time TDVP step on the GPU and one in
+    the oracle, both from the oracle's prepared state."""
+    from paper_2003_13245_amd import api
+    H, _ = api.mpo_build(ctx, c.m)
+    g = api.mps_from_host(ctx, c.psi.A)
+    api.tdvp_step(ctx, H, g, dt_real=c.r.dt)
+    o = c.psi.copy()
+    o.log_norm = 0.0
+    T.tdvp_step(o, c.Hw, -1j * c.r.dt)
+    d = mps_rel_distance(download_mps(g, c.dims), o)
+    say(f"[e2e] {c.name}: one-step GPU/oracle distance {d:.1e}")
+    assert d < 1e-12, d
+    return d
+
+
 def gpu_prep(ctx, c):
     from paper_2003_13245_amd import api
     H, J = api.mpo_build(ctx, c.m)
@@ -166,6 +209,7 @@ def test_corr_from_common_state(ctx, name):
     """C(t) on the GPU from the oracle's |Psi_beta>, against the oracle."""
     from paper_2003_13245_amd import api
     c = case(name)
+    c.set_step_noise(one_step_difference(ctx, c))
     H, J = api.mpo_build(ctx, c.m)
     say(f"[e2e] {name}: gpu dynamics from the oracle state")
     psi = api.mps_from_host(ctx, c.psi.A)
@@ -184,6 +228,7 @@ def test_pipeline(ctx, name):
     own spread between the two SVD drivers, and never tighter than 1e-3."""
     from paper_2003_13245_amd import api
     c = case(name)
+    c.set_step_noise(one_step_difference(ctx, c))
     say(f"[e2e] {name}: gpu pipeline")
     H, J, psi_g, _ = gpu_prep(ctx, c)
     C_g = api.corr_current(ctx, H, J, psi_g, c.r.D, c.r.dt, c.cfg["steps"], cutoff=c.cut)
