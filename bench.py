@@ -67,6 +67,86 @@ class Roctx:
             self.lib.roctxProfilerPause(0)
 
 
+def gemm_source_sha256():
+    import hashlib
+    path = os.path.join(HERE, "paper_2003_13245_amd", "csrc", "gemm.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel, workload_name):
+    """HBM bytes per launch of `kernel` from the committed counter record
+    (two rocprofv3 --pmc passes, FETCH_SIZE then WRITE_SIZE, calibrated by a
+    copy of known size), or None when there is none for this kernel and
+    workload or the kernel source changed since it was taken."""
+    path = os.path.join(HERE, "profiles", f"traffic_{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel") != kernel or rec.get("gemm_source_sha256") != gemm_source_sha256():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
+def summarize(kind, csv_path, log_path):
+    """Summary of rocprofv3 CSV rows (kernel trace or counter collection)
+    whose dispatch started inside the first timed window this script printed
+    to `log_path` ("[bench] timed region boottime_ns t0 t1")."""
+    import collections
+    import csv
+    import re
+    windows = {}
+    with open(log_path) as f:
+        for line in f:
+            for label, pat in (("timed steps", r"timed region boottime_ns (\d+) (\d+)"),
+                               ("calibration copy",
+                                r"calibration copy of \d+ bytes boottime_ns (\d+) (\d+)")):
+                m = re.search(pat, line)
+                if m and label not in windows:
+                    windows[label] = (int(m.group(1)), int(m.group(2)))
+    if "timed steps" not in windows:
+        raise SystemExit("no timed window in the log")
+    sel = {k: [] for k in windows}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            st = int(row["Start_Timestamp"])
+            for k, (a, b) in windows.items():
+                if a <= st <= b:
+                    sel[k].append(row)
+    for label in windows:
+        summarize_rows(kind, label, windows[label], sel[label])
+
+
+def summarize_rows(kind, label, window, rows):
+    import collections
+    t0, t1 = window
+    out = [f"[{label}] window {(t1 - t0) / 1e9:.3f} s, dispatches in window {len(rows)}"]
+    if kind == "trace":
+        acc = collections.defaultdict(lambda: [0, 0, 0, 1 << 62])
+        for row in rows:
+            d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+            a = acc[row["Kernel_Name"]]
+            a[0] += 1
+            a[1] += d
+            a[2] = max(a[2], d)
+            a[3] = min(a[3], d)
+        tot = sum(a[1] for a in acc.values())
+        out.append(f"kernel time in window {tot / 1e6:.1f} ms (summed over both streams)")
+        out.append("calls\ttotal_ms\tavg_us\tmin_us\tmax_us\tshare\tkernel")
+        for name, (n, t, mx, mn) in sorted(acc.items(), key=lambda kv: -kv[1][1])[:30]:
+            out.append(f"{n}\t{t / 1e6:.2f}\t{t / n / 1e3:.2f}\t{mn / 1e3:.2f}\t{mx / 1e3:.2f}\t"
+                       f"{100 * t / tot:.1f}%\t{name[:100]}")
+    else:
+        acc = collections.defaultdict(list)
+        for row in rows:
+            acc[(row["Kernel_Name"], row["Counter_Name"])].append(float(row["Counter_Value"]))
+        out.append("counter\tdispatches\tsum_KiB\tmax_KiB\tkernel")
+        for (name, cn), v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+            out.append(f"{cn}\t{len(v)}\t{sum(v):.6g}\t{max(v):.6g}\t{name[:100]}")
+    print("\n".join(out))
+
+
 def kernel_name(kind):
     """Name of the GEMM kernel instance with identity `kind` (see ftd_stats)."""
     tin = "double" if (kind >> 3) == 0 else "float"
@@ -168,7 +248,13 @@ def main():
                     help="library progress lines on stderr (0 silent, 2 per compression)")
     ap.add_argument("--krylov-tol", type=float, default=None,
                     help="Lanczos stop tolerance (default: the workload's)")
+    ap.add_argument("--summarize", nargs=3, metavar=("KIND", "CSV", "LOG"),
+                    help="summarise rocprofv3 CSV rows (KIND trace or pmc) of the timed window "
+                         "recorded in LOG, then exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(*args.summarize)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -214,9 +300,12 @@ def main():
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         roctx.resume()
+        c0 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
         dst.copy_(src)
         torch.cuda.synchronize()
+        c1 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
         roctx.pause()
+        log(f"[bench] calibration copy of {n * 4} bytes boottime_ns {c0} {c1}")
         del src, dst
     sps = args.steps / el_mix
     log(f"[bench] mixed: {el_mix / args.steps * 1e3:.1f} ms/step, H_eff "
@@ -241,7 +330,8 @@ def main():
     achieved = st["dom_flops"] / max(st["dom_ms"], 1e-12) / 1e9     # TFLOP/s
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision],
                        "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
-                       "traffic": None, "kernel": kernel_name(st["dom_kind"]),
+                       "traffic": measured_traffic(kernel_name(st["dom_kind"]), wl.name),
+                       "kernel": kernel_name(st["dom_kind"]),
                        "avg_launch_ms": dom_avg_ms, "launches": st["dom_launches"],
                        "algorithmic_bytes_per_launch":
                            st["dom_bytes"] / max(st["dom_launches"], 1),

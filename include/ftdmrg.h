@@ -108,7 +108,8 @@ const char* ftd_last_error(void);
  * H_eff / K_eff matvecs since the last reset: number of launches, summed
  * kernel milliseconds and summed algorithmic flops (8 m n k per complex
  * product), each bracketed by events; the same for the single GEMM kernel
- * instance with the largest time share (dom_*), whose launches are timed on
+ * instance with the largest time share over all H_eff and K_eff launches
+ * (dom_*; those matvecs share kernel instances), whose launches are timed on
  * the device (first block start to last block end, the kernel alone without
  * its split-K reduction); and over the whole context the number of matvecs
  * and Krylov vectors.  Statistics are reset by ftd_ctx_stats_reset. */

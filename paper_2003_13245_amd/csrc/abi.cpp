@@ -209,8 +209,9 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
                 s.heff_ms += ms;
                 s.heff_flops += e.flops;
             }
-            if (e.tag == TAG_HEFF) {
-                // the kernel alone: its device timestamps (first block start to
+            if (e.tag == TAG_HEFF || e.tag == TAG_KEFF) {
+                // every launch of a kernel instance (H_eff and K_eff matvecs share
+                // instances); the kernel alone: its device timestamps (first block start to
                 // last block end), else the events around the main launch
                 float kms_one = ms;
                 const auto& sl = slots[owner[ie]];
