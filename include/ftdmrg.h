@@ -43,8 +43,10 @@ typedef enum {
     FTD_C128 = 0,        /* every contraction in complex float64               */
     FTD_C64 = 1,         /* contractions in complex float32 on MFMA, Krylov,
                             QR, norms and log Z in float64                     */
-    FTD_BF16X3 = 2       /* contractions as three bf16 split products with
-                            float32 accumulation; float64 elsewhere            */
+    FTD_BF16X3 = 2       /* reserved for contractions as three bf16 split
+                            products with float32 accumulation: not built,
+                            every call that takes a precision rejects it with
+                            FTD_EINVAL                                         */
 } ftd_precision;
 
 typedef struct ftd_ctx ftd_ctx;

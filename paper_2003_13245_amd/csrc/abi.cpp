@@ -40,7 +40,8 @@ static void check_krylov(const ftd_krylov_opts* ko, double& tol, int& mmax) {
 }
 
 static Prec to_prec(int32_t p) {
-    FTD_CHECK(p == FTD_C128 || p == FTD_C64 || p == FTD_BF16X3, FTD_EINVAL, "unknown precision");
+    FTD_CHECK(p != FTD_BF16X3, FTD_EINVAL, "bf16x3 contractions are not built");
+    FTD_CHECK(p == FTD_C128 || p == FTD_C64, FTD_EINVAL, "unknown precision");
     return static_cast<Prec>(p);
 }
 

@@ -161,3 +161,12 @@ def test_tdvp_pair_matches_two_steps(ctx, kind):
         assert mps_rel_distance(x, y) < 1e-13
     with pytest.raises(api.FtdError):
         api.tdvp_pair(ctx, H, ga, ga, **kw)
+
+
+def test_unbuilt_precision_is_rejected(ctx):
+    from paper_2003_13245_amd import api
+    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2)
+    dims = Mdl.site_dims(m)
+    g = api.mps_from_host(ctx, random_mps(dims, 3, np.random.default_rng(1), 0).A)
+    with pytest.raises(api.FtdError):
+        g.set_precision("bf16x3")
