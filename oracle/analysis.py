@@ -66,3 +66,12 @@ def mean_free_path(C, dt):
     r = np.abs(C.real / C[0].real)
     tau = dt * (r.sum() - 0.5 * (r[0] + r[-1]))
     return v * tau, v, tau
+
+
+def coherent_length(sigma):
+    """L = (sum_ij |sigma_ij|)^2 / (N sum_ij |sigma_ij|^2) of the reduced
+    electronic density sigma (N x N): 1 for sigma = I/N (localised), N for
+    |sigma_ij| = 1/N (delocalised)."""
+    a = np.abs(np.asarray(sigma))
+    N = a.shape[0]
+    return float(a.sum() ** 2 / (N * (a * a).sum()))

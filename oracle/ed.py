@@ -130,6 +130,14 @@ class EDResult:
     def energy(self):
         return float(self.w @ self.E)
 
+    def reduced_density(self):
+        """sigma = Tr_ph rho_beta (N x N): sigma_ij = sum_v rho[(i v), (j v)]
+        = Tr[rho c+_j c_i] (the coherent-length passage)."""
+        N = self.model.n_mol
+        nph = self.dim // N
+        rho = (self.U * self.w) @ self.U.T
+        return np.einsum("ivjv->ij", rho.reshape(N, nph, N, nph))
+
     def density_expectation(self):
         """<c+_n c_n> in the thermal state, per molecule."""
         N = self.model.n_mol

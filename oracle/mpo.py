@@ -74,6 +74,17 @@ def current_mpo(model):
     return build_mpo(model, M.current_terms(model))
 
 
+def hop_mpo(model, i, j):
+    """MPO of c+_j c_i (moves the carrier from molecule i to molecule j; the
+    number operator n_i when i == j).  With one carrier the hard-core string
+    between the two sites is +1."""
+    idx = M.index_of(model)
+    ei, ej = idx[("e", i, -1)], idx[("e", j, -1)]
+    if i == j:
+        return build_mpo(model, [(1.0, [(ei, "n")])])
+    return build_mpo(model, [(1.0, [(ej, "sp"), (ei, "sm")])])
+
+
 def densify(Ws):
     """Dense matrix of an MPO on the full product space (tiny chains only)."""
     T = Ws[0][0]                      # [wr, d, d]

@@ -518,6 +518,19 @@ def thermal_prep(model, Hw, beta, n_imag, n_grow, D, cutoff=1e-10, tol=1e-14,
     return psi, 2.0 * psi.log_norm
 
 
+def reduced_density(model, psi):
+    """sigma_ij = <psi| c+_j c_i |psi> / <psi|psi> (operators on the P leg;
+    the inner product traces P and Q)."""
+    from . import mpo as OM
+    N = model.n_mol
+    nrm2 = norm(psi) ** 2
+    sig = np.zeros((N, N), dtype=complex)
+    for i in range(N):
+        for j in range(N):
+            sig[i, j] = overlap(psi, OM.hop_mpo(model, i, j), psi) / nrm2
+    return sig
+
+
 def apply_current(Jw, psi, D, cutoff=1e-10):
     """j|psi> compressed to bond dimension D (norm kept, log_norm reset)."""
     phi = compress_terms([(1.0, Jw, psi)], D, cutoff)

@@ -394,3 +394,57 @@ def test_adaptive_growth_matches_fixed_count():
     psi_f, lz_f = T.thermal_prep(m, Hw, r.beta, 6, st.growth_steps, 8)
     assert psi_a.bond_dims() == psi_f.bond_dims()
     assert abs(lz_a - lz_f) < 1e-13
+
+
+# --------------------------------------------------------- coherent length
+@pytest.mark.parametrize("kind", ["holstein", "peierls"])
+def test_reduced_density_sum_rule_and_symmetries(kind):
+    """sigma = Tr_ph rho: unit trace (one carrier), Hermitian, and invariant
+    under translation along the periodic ring."""
+    m = small_model(n_mol=4, n_loc=1, n_nl=1 if kind == "peierls" else 0,
+                    levels=2 if kind == "peierls" else 3)
+    s = ED.EDResult(m, 0.8).reduced_density()
+    N = m.n_mol
+    assert abs(np.trace(s) - 1) < 1e-13
+    assert np.abs(s - s.conj().T).max() < 1e-13
+    for i in range(N):
+        for j in range(N):
+            assert abs(s[i, j] - s[(i + 1) % N, (j + 1) % N]) < 1e-12
+
+
+def test_coherent_length_limits():
+    """The paper's two limits: sigma = I/N gives L = 1 (infinite temperature,
+    where the one-carrier thermal state is uniform), and a completely
+    delocalised state (g = 0 ring at low temperature: the band-edge Bloch
+    state) gives L = N."""
+    N = 5
+    assert abs(An.coherent_length(np.eye(N) / N) - 1) < 1e-14
+    assert abs(An.coherent_length(np.full((N, N), 1 / N)) - N) < 1e-13
+    m = small_model(n_mol=4, n_loc=1, levels=3)
+    assert abs(An.coherent_length(ED.EDResult(m, 0.0).reduced_density()) - 1) < 1e-12
+    m0 = W.Model(n_mol=4, periodic=1, omega_loc=[1.0], g_loc=[0.0], omega_nl=[], g_nl=[],
+                 levels_loc=2, levels_nl=1, V=1.0)
+    L = An.coherent_length(ED.EDResult(m0, 30.0).reduced_density())
+    assert abs(L - 4) < 1e-10
+
+
+def test_reduced_density_from_full_rank_mps_equals_ed():
+    """sigma from the MPS expectation values of c+_j c_i (the two-point MPO)
+    on the exact purified thermal state equals the partial trace of the
+    dense thermal density matrix."""
+    m, dims, Hw, _ = _full_rank_setup()
+    beta = 0.9
+    r = ED.EDResult(m, beta)
+    v0 = T.to_dense(T.identity_mps(m))
+    Mb = sla.expm(-0.5 * beta * OM.densify(Hw))
+    L = len(dims)
+    n = int(np.prod(dims))
+    # to_dense interleaves the legs (p1 q1 ... pL qL): apply Mb on the P legs
+    t = v0.reshape([d for d in dims for _ in (0, 1)])
+    perm = list(range(0, 2 * L, 2)) + list(range(1, 2 * L, 2))
+    t = np.transpose(t, perm).reshape(n, n)
+    t = (Mb @ t).reshape([d for d in dims] * 2)
+    vb = np.transpose(t, np.argsort(perm)).reshape(-1)
+    psi = T.full_rank_mps(vb, dims)
+    s = T.reduced_density(m, psi)
+    assert np.abs(s - r.reduced_density()).max() < 1e-12
