@@ -273,6 +273,27 @@ ftd_status ftd_fgr_corr(const double* t, int32_t nt, const double* omega, const 
                         int32_t n_modes, double V, double beta, double e0, double R,
                         double* C_out);
 
+/* Electronic reduced density matrix of a (purified) state, the phonon trace
+ * of the coherent-length section: sigma = Tr_ph rho with rho = |psi><psi| /
+ * <psi|psi> traced over the ancillas, i.e.
+ *   sigma_ij = <psi| c+_j c_i |psi> / <psi|psi>,
+ * each element one FP64 overlap with a bond-dimension-1 product MPO (sigma-
+ * on e_i, sigma+ on e_j; n_i on the diagonal; no string is needed in the
+ * one-carrier sector).  For psi_beta, Tr sigma = 1 and sigma is Hermitian.
+ * m: the model psi was prepared for (validated as in ftd_mpo_build; its
+ * chain must match psi's).  sigma: host, 2*N*N doubles, interleaved complex,
+ * row i column j.  Cost: N^2 overlaps.  Errors: FTD_EINVAL (null, model
+ * mismatch, zero norm). */
+ftd_status ftd_reduced_density(ftd_ctx* ctx, const ftd_model* m, const ftd_mps* psi,
+                               double* sigma);
+
+/* Coherent length of the coherent-length equation,
+ *   L = (sum_ij |sigma_ij|)^2 / (N sum_ij |sigma_ij|^2),
+ * 1 for a fully localised and N for a fully delocalised thermal state.
+ * sigma: host, 2*n*n doubles (interleaved complex).  Host-only.  Errors:
+ * FTD_EINVAL (n < 1, non-finite or all-zero sigma). */
+ftd_status ftd_coherent_length(const double* sigma, int32_t n, double* L);
+
 /* ------------------------------------------------- kernel-level entry points
  * Apply the one-site effective Hamiltonian of `site` to x, with the left
  * environment built from sites < site of psi (assumed left-orthonormal there)

@@ -90,6 +90,8 @@ SIGNATURES = {
     "ftd_mobility": (I32, [DP, I32, D, D, D, DP, DP]),
     "ftd_mean_free_path": (I32, [DP, I32, D, D, DP, DP, DP]),
     "ftd_fgr_corr": (I32, [DP, I32, DP, DP, I32, D, D, D, D, DP]),
+    "ftd_reduced_density": (I32, [P, P, P, DP]),
+    "ftd_coherent_length": (I32, [DP, I32, DP]),
     "ftd_heff_apply": (I32, [P, P, P, I32, DP, DP, I32]),
     "ftd_svd_trunc": (I32, [P, I32, I32, DP, I32, D, I32, DP, DP, I32P]),
     "ftd_gemm": (I32, [P, I32, I32, I32, I32, I32, I32, DP, DP, DP]),

@@ -27,8 +27,9 @@ def _mark_shutdown():
 
 
 __all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_pair",
-           "corr_current", "mobility", "apply_compress", "overlap", "heff_apply",
-           "mps_from_host", "gemm", "FtdError"]
+           "corr_current", "mobility", "mean_free_path", "fgr_corr", "reduced_density",
+           "coherent_length", "apply_compress", "overlap", "heff_apply", "mps_from_host",
+           "gemm", "FtdError"]
 
 
 class Context:
@@ -275,6 +276,29 @@ def fgr_corr(t, V, omega, g, beta, e0=1.0, R=1.0):
                            int(om.size), float(V), float(beta), float(e0), float(R),
                            _abi._dptr(out)))
     return out[0::2] + 1j * out[1::2]
+
+
+def reduced_density(ctx, model, psi):
+    """sigma_ij = <psi|c+_j c_i|psi>/<psi|psi> (N x N complex) for a state of `model`."""
+    m, keep = _model_struct(model)
+    n = int(model.n_mol)
+    out = np.empty(2 * n * n)
+    check(lib.ftd_reduced_density(ctx.h, C.byref(m), psi.h, _abi._dptr(out)))
+    return (out[0::2] + 1j * out[1::2]).reshape(n, n)
+
+
+def coherent_length(sigma):
+    """L = (sum |sigma_ij|)^2 / (N sum |sigma_ij|^2)."""
+    s = np.asarray(sigma, dtype=np.complex128)
+    n = s.shape[0]
+    if s.shape != (n, n):
+        raise ValueError("sigma must be square")
+    buf = np.empty(2 * n * n)
+    buf[0::2] = s.real.reshape(-1)
+    buf[1::2] = s.imag.reshape(-1)
+    L = C.c_double()
+    check(lib.ftd_coherent_length(_abi._dptr(buf), int(n), C.byref(L)))
+    return L.value
 
 
 def mps_from_host(ctx, tensors, log_norm=0.0, precision="c128"):

@@ -248,9 +248,7 @@ ftd_status ftd_ctx_synchronize(ftd_ctx* ctx) {
     });
 }
 
-ftd_status ftd_mpo_build(ftd_ctx* ctx, const ftd_model* m, ftd_mpo** H, ftd_mpo** J) {
-    return guarded([&] {
-        FTD_CHECK(ctx && m && H && J, FTD_EINVAL, "null argument");
+static void check_model(const ftd_model* m) {
         FTD_CHECK(m->n_mol >= (m->periodic ? 3 : 2), FTD_EINVAL,
                   "need n_mol >= 3 on a ring (>= 2 open)");
         FTD_CHECK(m->n_loc >= 0 && m->n_nl >= 0, FTD_EINVAL, "negative mode count");
@@ -265,6 +263,12 @@ ftd_status ftd_mpo_build(ftd_ctx* ctx, const ftd_model* m, ftd_mpo** H, ftd_mpo*
             FTD_CHECK(fin(m->omega_loc[i]) && fin(m->g_loc[i]), FTD_EINVAL, "non-finite local mode");
         for (int i = 0; i < m->n_nl; ++i)
             FTD_CHECK(fin(m->omega_nl[i]) && fin(m->g_nl[i]), FTD_EINVAL, "non-finite bond mode");
+}
+
+ftd_status ftd_mpo_build(ftd_ctx* ctx, const ftd_model* m, ftd_mpo** H, ftd_mpo** J) {
+    return guarded([&] {
+        FTD_CHECK(ctx && m && H && J, FTD_EINVAL, "null argument");
+        check_model(m);
         Ctx* c = &ctx->c;
         Mpo* h = build_mpo(c, *m, false);
         Mpo* j = nullptr;
@@ -617,6 +621,31 @@ ftd_status ftd_mobility(const double* C, int32_t n, double dt, double beta, doub
         const double e = 1.602176634e-19, a0 = 5.29177210903e-11, hbar = 1.054571817e-34;
         *mu_au = mu;
         *mu_cm2Vs = mu * e * a0 * a0 / hbar * 1e4;
+    });
+}
+
+ftd_status ftd_reduced_density(ftd_ctx* ctx, const ftd_model* m, const ftd_mps* psi,
+                               double* sigma) {
+    return guarded([&] {
+        FTD_CHECK(ctx && m && psi && sigma, FTD_EINVAL, "null argument");
+        check_model(m);
+        reduced_density(&ctx->c, *m, psi->m, sigma);
+    });
+}
+
+ftd_status ftd_coherent_length(const double* sigma, int32_t n, double* L) {
+    return guarded([&] {
+        FTD_CHECK(sigma && L, FTD_EINVAL, "null argument");
+        FTD_CHECK(n >= 1, FTD_EINVAL, "n must be >= 1");
+        double s1 = 0.0, s2 = 0.0;
+        for (int64_t k = 0; k < (int64_t)n * n; ++k) {
+            const double a = std::hypot(sigma[2 * k], sigma[2 * k + 1]);
+            FTD_CHECK(std::isfinite(a), FTD_EINVAL, "non-finite sigma");
+            s1 += a;
+            s2 += a * a;
+        }
+        FTD_CHECK(s2 > 0.0, FTD_EINVAL, "sigma is zero");
+        *L = s1 * s1 / ((double)n * s2);
     });
 }
 

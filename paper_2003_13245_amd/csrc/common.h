@@ -311,6 +311,8 @@ void timing_slots_reset(Ctx* ctx);
 // ---------------------------------------------------------- high level ops
 Mpo* build_mpo(Ctx* ctx, const ftd_model& m, bool current);
 void upload_mpo(Ctx* ctx, Mpo* mpo);
+Mpo* build_product_mpo(Ctx* ctx, const ftd_model& md, std::vector<int>& carrier);
+void reduced_density(Ctx* ctx, const ftd_model& md, const Mps* psi, double* sigma);
 void destroy_mpo(Mpo* mpo);
 
 Mps* mps_alloc(Ctx* ctx, const std::vector<int>& Dl, const std::vector<int>& d,

@@ -1424,6 +1424,53 @@ Mps* taylor_growth(Ctx* ctx, const Mpo* H, const Mps* psi, double dtau, int D, d
 
 // ============================================================== overlap
 // <bra| O |ket> by a left-to-right transfer contraction in float64.
+// sigma_ij = <psi| c+_j c_i |psi> / <psi|psi>: one bond-1 MPO whose two
+// carrier-site op tables are rewritten per pair (sigma- on e_i, sigma+ on e_j;
+// n on e_i when i == j), each pair one overlap.  sigma: 2*N*N doubles,
+// interleaved complex, row i column j.
+void reduced_density(Ctx* ctx, const ftd_model& md, const Mps* psi, double* sigma) {
+    std::vector<int> epos;
+    Mpo* O = build_product_mpo(ctx, md, epos);
+    try {
+        FTD_CHECK(O->L == psi->L, FTD_EINVAL, "state and model have different chains");
+        for (int s = 0; s < O->L; ++s)
+            FTD_CHECK(O->s[s].d == psi->d[s], FTD_EINVAL, "state and model have different sites");
+        upload_mpo(ctx, O);
+        // electron basis |0> empty, |1> occupied; op tables [re plane][im plane], [out][in]
+        const double eye[8] = {1, 0, 0, 1, 0, 0, 0, 0};
+        const double sm[8] = {0, 1, 0, 0, 0, 0, 0, 0};   // |0><1|
+        const double sp[8] = {0, 0, 1, 0, 0, 0, 0, 0};   // |1><0|
+        const double nn[8] = {0, 0, 0, 1, 0, 0, 0, 0};
+        auto put = [&](int site, const double* op) {
+            FTD_HIP(hipMemcpyAsync(O->s[site].ops64, op, sizeof(double) * 8, hipMemcpyHostToDevice,
+                                   ctx->stream));
+        };
+        const double z = overlap(ctx, psi, O, psi).real();
+        FTD_CHECK(z > 0.0 && std::isfinite(z), FTD_EINVAL, "state has zero norm");
+        const int N = md.n_mol;
+        for (int i = 0; i < N; ++i) {
+            for (int j = 0; j < N; ++j) {
+                if (i == j) {
+                    put(epos[i], nn);
+                } else {
+                    put(epos[i], sm);
+                    put(epos[j], sp);
+                }
+                const cplx v = overlap(ctx, psi, O, psi) / z;
+                sigma[2 * (i * N + j)] = v.real();
+                sigma[2 * (i * N + j) + 1] = v.imag();
+                put(epos[i], eye);
+                put(epos[j], eye);
+            }
+        }
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+    } catch (...) {
+        destroy_mpo(O);
+        throw;
+    }
+    destroy_mpo(O);
+}
+
 cplx overlap(Ctx* ctx, const Mps* bra, const Mpo* O, const Mps* ket) {
     const int L = bra->L;
     FTD_CHECK(ket->L == L && O->L == L, FTD_EINVAL, "overlap: lengths differ");

@@ -225,6 +225,46 @@ Mpo* build_mpo(Ctx* ctx, const ftd_model& md, bool current) {
     return mpo;
 }
 
+// Bond-dimension-1 MPO of a product of local operators, all identities as
+// built: the chain layout of build_mpo, one channel per bond.  Entries on
+// carrier sites are flagged non-identity so that their device op tables,
+// which the caller overwrites (e.g. with sigma- and sigma+ for c+_j c_i), are
+// always applied.  carrier[n] receives the chain position of e_n.
+Mpo* build_product_mpo(Ctx* ctx, const ftd_model& md, std::vector<int>& carrier) {
+    const int N = md.n_mol, ML = md.n_loc, MN = md.n_nl;
+    const bool per = md.periodic != 0;
+    std::vector<int> dims;
+    carrier.assign(N, -1);
+    for (int n = 0; n < N; ++n) {
+        carrier[n] = (int)dims.size();
+        dims.push_back(2);
+        for (int m = 0; m < ML; ++m) dims.push_back(md.levels_loc);
+        if (per || n < N - 1)
+            for (int m = 0; m < MN; ++m) dims.push_back(md.levels_nl);
+    }
+    Mpo* mpo = new Mpo();
+    mpo->ctx = ctx;
+    mpo->L = (int)dims.size();
+    mpo->s.resize(mpo->L);
+    mpo->electronic.assign(mpo->L, 0);
+    for (int n = 0; n < N; ++n) mpo->electronic[carrier[n]] = 1;
+    for (int s = 0; s < mpo->L; ++s) {
+        MpoSite& S = mpo->s[s];
+        S.d = dims[s];
+        S.wl = S.wr = 1;
+        // no I/F channel semantics: never used to build environments
+        S.idxI_l = S.idxF_l = S.idxI_r = S.idxF_r = -1;
+        MpoEntry e;
+        e.cl = e.cr = 0;
+        e.identity = !mpo->electronic[s];
+        e.op = op_identity(S.d);
+        S.ents.push_back(std::move(e));
+        mpo->wmax = std::max(mpo->wmax, 1);
+        mpo->dmax = std::max(mpo->dmax, S.d);
+    }
+    return mpo;
+}
+
 void upload_mpo(Ctx* ctx, Mpo* mpo) {
     for (auto& S : mpo->s) {
         const int d = S.d;

@@ -121,3 +121,23 @@ def test_fgr_corr_rejects_bad_modes(abi):
         api.fgr_corr(np.zeros(3), 0.1, [0.0], [1.0], 1.0)
     with pytest.raises(abi.FtdError):
         api.fgr_corr(np.zeros(3), 0.1, [1.0], [1.0], 0.0)
+
+
+def test_coherent_length_host_entry(abi):
+    from oracle import analysis as An
+    from paper_2003_13245_amd import api
+    rng = np.random.default_rng(4)
+    for n in (1, 3, 21):
+        s = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        s = s @ s.conj().T
+        a, b = An.coherent_length(s), api.coherent_length(s)
+        assert abs(a - b) <= 1e-13 * a
+    # the two limits the coherent-length definition names
+    assert abs(api.coherent_length(np.eye(5) / 5) - 1.0) < 1e-14
+    assert abs(api.coherent_length(np.full((5, 5), 0.2)) - 5.0) < 1e-13
+    for bad in (np.zeros((3, 3)), np.full((2, 2), np.nan)):
+        with pytest.raises(api.FtdError):
+            api.coherent_length(bad)
+    import ctypes
+    L = ctypes.c_double()
+    assert abi.lib.ftd_coherent_length(abi._dptr(np.zeros(2)), 0, ctypes.byref(L)) != 0
