@@ -304,6 +304,18 @@ ftd_status ftd_coherent_length(const double* sigma, int32_t n, double* L);
 ftd_status ftd_heff_apply(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, int32_t site,
                           const double* x, double* y, int32_t n_repeat);
 
+/* Gauge move of the TDVP sweep on the device (shifted CholeskyQR in three
+ * passes, the orthonormalisation the projector-splitting integrator needs
+ * between a site and the next bond): lq = 0: M (rows x cols, rows >= cols,
+ * full column rank) = Q R, Q with orthonormal columns, R upper triangular with
+ * a real positive diagonal; lq = 1: M (rows <= cols, full row rank) = L Q, Q
+ * with orthonormal rows, L lower triangular with a real positive diagonal.
+ * M, Q: host, rows*cols interleaved complex, row-major; F: host, k*k with
+ * k = min(rows, cols), receives R or L.  Errors: FTD_EINVAL (shapes),
+ * FTD_ENOCONV (Cholesky breakdown: M numerically rank deficient). */
+ftd_status ftd_qr(ftd_ctx* ctx, int32_t rows, int32_t cols, const double* M, int32_t lq,
+                  double* Q, double* F);
+
 /* Truncated SVD on the device (the compression kernel): T (M x N, host,
  * interleaved complex, row-major) ~ L diag(S) R with L (M x k) orthonormal
  * columns and R (k x N) orthonormal rows, keeping at most D singular values

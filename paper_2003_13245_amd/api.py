@@ -28,7 +28,7 @@ def _mark_shutdown():
 
 __all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_pair",
            "corr_current", "mobility", "mean_free_path", "fgr_corr", "reduced_density",
-           "coherent_length", "apply_compress", "overlap", "heff_apply", "mps_from_host",
+           "coherent_length", "qr", "apply_compress", "overlap", "heff_apply", "mps_from_host",
            "gemm", "FtdError"]
 
 
@@ -299,6 +299,23 @@ def coherent_length(sigma):
     L = C.c_double()
     check(lib.ftd_coherent_length(_abi._dptr(buf), int(n), C.byref(L)))
     return L.value
+
+
+def qr(ctx, M, lq=False):
+    """Device gauge factorisation: (Q, R) with M = Q R, or (L, Q) with M = L Q."""
+    M = np.ascontiguousarray(np.asarray(M, dtype=np.complex128))
+    rows, cols = M.shape
+    k = min(rows, cols)
+    buf = np.empty(2 * M.size)
+    buf[0::2] = M.real.reshape(-1)
+    buf[1::2] = M.imag.reshape(-1)
+    q = np.empty(2 * M.size)
+    f = np.empty(2 * k * k)
+    check(lib.ftd_qr(ctx.h, int(rows), int(cols), _abi._dptr(buf), int(bool(lq)), _abi._dptr(q),
+                     _abi._dptr(f)))
+    Q = (q[0::2] + 1j * q[1::2]).reshape(rows, cols)
+    F = (f[0::2] + 1j * f[1::2]).reshape(k, k)
+    return (F, Q) if lq else (Q, F)
 
 
 def mps_from_host(ctx, tensors, log_norm=0.0, precision="c128"):

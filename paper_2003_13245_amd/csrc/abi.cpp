@@ -742,6 +742,49 @@ ftd_status ftd_svd_trunc(ftd_ctx* ctx, int32_t M, int32_t N, const double* T, in
     });
 }
 
+ftd_status ftd_qr(ftd_ctx* ctx, int32_t rows, int32_t cols, const double* M, int32_t lq,
+                  double* Q, double* F) {
+    return guarded([&] {
+        FTD_CHECK(ctx && M && Q && F, FTD_EINVAL, "null argument");
+        FTD_CHECK(rows >= 1 && cols >= 1, FTD_EINVAL, "bad sizes");
+        FTD_CHECK(lq ? rows <= cols : rows >= cols, FTD_EINVAL,
+                  lq ? "ftd_qr: LQ needs rows <= cols" : "ftd_qr: QR needs rows >= cols");
+        Ctx* c = &ctx->c;
+        const int64_t n = (int64_t)rows * cols;
+        const int64_t k = lq ? rows : cols;
+        double* dM = static_cast<double*>(dev_alloc(c, sizeof(double) * 2 * n));
+        double* dF = static_cast<double*>(dev_alloc(c, sizeof(double) * 2 * k * k));
+        try {
+            std::vector<double> t(2 * n);
+            for (int64_t i = 0; i < n; ++i) {
+                t[i] = M[2 * i];
+                t[i + n] = M[2 * i + 1];
+            }
+            FTD_HIP(hipMemcpy(dM, t.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice));
+            if (lq)
+                lq_chol(c, dM, rows, cols, dF, true);
+            else
+                qr_chol(c, dM, rows, cols, dF, true);
+            auto down = [&](const double* d, int64_t cnt, double* h) {
+                std::vector<double> b(2 * cnt);
+                FTD_HIP(hipMemcpy(b.data(), d, sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost));
+                for (int64_t i = 0; i < cnt; ++i) {
+                    h[2 * i] = b[i];
+                    h[2 * i + 1] = b[i + cnt];
+                }
+            };
+            down(dM, n, Q);
+            down(dF, k * k, F);
+        } catch (...) {
+            dev_free(c, dM);
+            dev_free(c, dF);
+            throw;
+        }
+        dev_free(c, dM);
+        dev_free(c, dF);
+    });
+}
+
 ftd_status ftd_gemm(ftd_ctx* ctx, int32_t precision, int32_t M, int32_t N, int32_t K,
                     int32_t transA, int32_t transB, const double* A, const double* B, double* C) {
     return guarded([&] {

@@ -107,6 +107,84 @@ __global__ void set_int_kernel(int* p, int v) { *p = v; }
 constexpr int kCholThreads = 256;
 __device__ __forceinline__ int pk(int i, int j, int n) { return i * n - (i * (i - 1)) / 2 + (j - i); }
 
+// G = I + E (the later CholeskyQR passes): the factor R = I + S, S = strict
+// upper part of E plus half its diagonal, and R^{-1} = I - S are exact up to
+// S^H S and S^2, whose entries are below n max|E|^2; taken when that bound is
+// under 1e-17 (below rounding).  Returns true when it wrote G and X.  Any
+// block size up to 1024; red holds one double per wavefront.
+__device__ bool chol_near_identity(double* G, double* X, int n, int64_t plane, int* converged,
+                                   double* red) {
+    const int tid = threadIdx.x, nt = blockDim.x, nn = n * n;
+    double mx = 0.0;
+    for (int base = 0; base < nn; base += 4 * nt) {
+        double vr[4], vi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = base + u * nt + tid;
+            vr[u] = e < nn ? G[e] : 0.0;
+            vi[u] = e < nn ? G[e + plane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = base + u * nt + tid;
+            if (e < nn) {
+                const int i = e / n, j = e - i * n;
+                mx = fmax(mx, fmax(fabs(vr[u] - ((i == j) ? 1.0 : 0.0)), fabs(vi[u])));
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    double m = 0.0;
+    for (int w = 0; w < nt / 64; ++w) m = fmax(m, red[w]);
+    if ((double)n * m * m > 1e-17) return false;
+    // Q was already orthonormal to 1e-9: the next pass could only move it at
+    // the rounding level
+    if (converged && tid == 0 && m <= 1e-9) converged[0] = 1;
+    for (int e = tid; e < nn; e += nt) {
+        const int i = e / n, j = e - i * n;
+        double sr = 0.0, si = 0.0;
+        if (j > i) {
+            sr = G[e];
+            si = G[e + plane];
+        } else if (j == i) {
+            sr = 0.5 * (G[e] - 1.0);
+        }
+        G[e] = ((i == j) ? 1.0 : 0.0) + sr;
+        G[e + plane] = si;
+        X[e] = ((i == j) ? 1.0 : 0.0) - sr;
+        X[e + plane] = -si;
+    }
+    return true;
+}
+
+// upper triangle of G (+ shift on the diagonal, real diagonal) into packed
+// LDS; four elements per thread in flight
+__device__ void chol_pack(const double* G, int n, int64_t plane, double s, double* Pr, double* Pi) {
+    const int tid = threadIdx.x, nt = blockDim.x, nn = n * n;
+    for (int base = 0; base < nn; base += 4 * nt) {
+        double vr[4], vi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = base + u * nt + tid;
+            vr[u] = e < nn ? G[e] : 0.0;
+            vi[u] = e < nn ? G[e + plane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = base + u * nt + tid;
+            if (e < nn) {
+                const int i = e / n, j = e - i * n;
+                if (j >= i) {
+                    Pr[pk(i, j, n)] = vr[u] + ((i == j) ? s : 0.0);
+                    Pi[pk(i, j, n)] = (i == j) ? 0.0 : vi[u];
+                }
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, double* X, int n,
                                                                     int64_t plane,
                                                                     const double* shift,
@@ -121,50 +199,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, d
     __shared__ double red[kCholThreads / 64];
     const int tid = threadIdx.x;
     const double s = shift ? shift[0] : 0.0;
-    if (!shift) {
-        // G = I + E (the later CholeskyQR passes): the factor R = I + S, S =
-        // strict upper part of E plus half its diagonal, and R^{-1} = I - S
-        // are exact up to S^H S and S^2, whose entries are below n max|E|^2;
-        // taken when that bound is under 1e-17 (below rounding)
-        double mx = 0.0;
-        for (int e = tid; e < n * n; e += kCholThreads) {
-            const int i = e / n, j = e - i * n;
-            const double er = G[e] - ((i == j) ? 1.0 : 0.0), ei = G[e + plane];
-            mx = fmax(mx, fmax(fabs(er), fabs(ei)));
-        }
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if ((tid & 63) == 0) red[tid >> 6] = mx;
-        __syncthreads();
-        double m = 0.0;
-        for (int w = 0; w < kCholThreads / 64; ++w) m = fmax(m, red[w]);
-        if ((double)n * m * m <= 1e-17) {
-            // Q was already orthonormal to 1e-9: the next pass could only move
-            // it at the rounding level
-            if (converged && tid == 0 && m <= 1e-9) converged[0] = 1;
-            for (int e = tid; e < n * n; e += kCholThreads) {
-                const int i = e / n, j = e - i * n;
-                double sr = 0.0, si = 0.0;
-                if (j > i) {
-                    sr = G[e];
-                    si = G[e + plane];
-                } else if (j == i) {
-                    sr = 0.5 * (G[e] - 1.0);
-                }
-                G[e] = ((i == j) ? 1.0 : 0.0) + sr;
-                G[e + plane] = si;
-                X[e] = ((i == j) ? 1.0 : 0.0) - sr;
-                X[e + plane] = -si;
-            }
-            return;
-        }
-    }
-    for (int e = tid; e < n * n; e += kCholThreads) {
-        const int i = e / n, j = e - i * n;
-        if (j >= i) {
-            Pr[pk(i, j, n)] = G[e] + ((i == j) ? s : 0.0);
-            Pi[pk(i, j, n)] = (i == j) ? 0.0 : G[e + plane];
-        }
-    }
+    if (!shift && chol_near_identity(G, X, n, plane, converged, red)) return;
+    chol_pack(G, n, plane, s, Pr, Pi);
     __syncthreads();
     // 256 threads as 8 rows x 32 columns for the trailing updates
     const int ty = tid >> 5, tx = tid & 31;
@@ -178,6 +214,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, d
                 piv = sqrt(dk);
             }
             Pr[pk(k, k, n)] = piv;
+            // the trailing updates leave a rounding-level imaginary part here
+            Pi[pk(k, k, n)] = 0.0;
         }
         __syncthreads();
         const double inv = 1.0 / piv;
@@ -241,6 +279,233 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, d
         __syncthreads();
     }
     for (int e = tid; e < n * n; e += kCholThreads) {
+        const int i = e / n, j = e - i * n;
+        X[e] = (j >= i) ? Pr[pk(i, j, n)] : 0.0;
+        X[e + plane] = (j >= i) ? Pi[pk(i, j, n)] : 0.0;
+    }
+}
+
+// Blocked variant of chol_inv_lds_kernel for 16 <= n <= 128, same contract
+// and packed LDS layout, 1024 threads (four wavefronts per SIMD hide the LDS
+// latency that bounds a single 256-thread workgroup), two workgroup barriers
+// per block of kCholBlk columns:
+//  factor, per block K: waves 0 and 1 factor the diagonal block in registers
+//    (lane = 8 r + c, pivots and rows exchanged by shuffles) and solve the
+//    block row R_KJ = R_KK^{-H} G_KJ, one column per lane; then every thread applies
+//    the rank-kCholBlk update G_JJ' -= R_KJ^H R_KJ' with its row's factors
+//    cached in registers;
+//  invert in place, per block J: eight lanes of the last wave invert the
+//    diagonal block (one column each) while the other threads form T = X_{:,<J} R_{<J,J} for
+//    its (row, column) pair into LDS; after a barrier X_{<J,J} = -T X_JJ.
+// Dynamic LDS: the packed triangle plus 2 * 128 * kCholBlk doubles for T.
+constexpr int kCholBlk = 8;
+constexpr int kBlkThreads = 1024;
+__global__ __launch_bounds__(kBlkThreads) void chol_inv_blk_kernel(double* G, double* X, int n,
+                                                                   int64_t plane,
+                                                                   const double* shift,
+                                                                   int* flag, const int* stop,
+                                                                   int* converged) {
+    if (stop && *stop) return;
+    extern __shared__ double lds[];
+    const int T = n * (n + 1) / 2;
+    double* Pr = lds;
+    double* Pi = lds + T;
+    double* Tr = lds + 2 * T;            // [row < 128][kCholBlk]
+    double* Ti = Tr + 128 * kCholBlk;
+    __shared__ double red[kBlkThreads / 64];
+    __shared__ double xdr[kCholBlk * kCholBlk], xdi[kCholBlk * kCholBlk];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const double s = shift ? shift[0] : 0.0;
+    if (!shift && chol_near_identity(G, X, n, plane, converged, red)) return;
+    chol_pack(G, n, plane, s, Pr, Pi);
+    __syncthreads();
+
+    // ------------------------------------------------------------ factor
+    const int ty = tid >> 5, tx = tid & 31;   // 32 row groups x 32 columns
+    for (int kb = 0; kb < n; kb += kCholBlk) {
+        const int nb = min(kCholBlk, n - kb);
+        if (wave < 2) {
+            // waves 0 and 1 both factor the diagonal block (identical
+            // arithmetic), then each solves its half of the block row
+            const int r = lane >> 3, c = lane & 7;
+            const bool own = r < nb && c < nb && r <= c;
+            double dr = 0.0, di = 0.0;
+            if (own) {
+                dr = Pr[pk(kb + r, kb + c, n)];
+                di = (r == c) ? 0.0 : Pi[pk(kb + r, kb + c, n)];
+            }
+            for (int k = 0; k < nb; ++k) {
+                double p = __shfl(dr, k * 8 + k, 64);
+                if (!(p > 0.0) || !isfinite(p)) {
+                    if (lane == 0 && wave == 0) flag[0] = 1;
+                    p = 1.0;
+                } else {
+                    p = sqrt(p);
+                }
+                const double ip = 1.0 / p;
+                if (own && r == k) {
+                    if (c == k) {
+                        dr = p;
+                        di = 0.0;
+                    } else {
+                        dr *= ip;
+                        di *= ip;
+                    }
+                }
+                const double kr = __shfl(dr, k * 8 + r, 64), ki = __shfl(di, k * 8 + r, 64);
+                const double cr = __shfl(dr, k * 8 + c, 64), ci = __shfl(di, k * 8 + c, 64);
+                if (own && r > k) {
+                    // G[r][c] -= conj(R[k][r]) R[k][c]
+                    dr -= kr * cr + ki * ci;
+                    di -= kr * ci - ki * cr;
+                }
+            }
+            if (own && wave == 0) {
+                Pr[pk(kb + r, kb + c, n)] = dr;
+                Pi[pk(kb + r, kb + c, n)] = di;
+            }
+            // block row: R_KK^H x = g, forward substitution, one column per
+            // lane; the factor comes from this wave's own registers
+            const int j = kb + nb + lane + 64 * wave;
+            const bool ok = j < n;
+            const int jj = ok ? j : n - 1;   // in-range address for idle lanes
+            double xr[kCholBlk], xi[kCholBlk];
+#pragma unroll
+            for (int k = 0; k < kCholBlk; ++k) {
+                xr[k] = 0.0;
+                xi[k] = 0.0;
+                if (k < nb) {
+                    const double dinv = 1.0 / __shfl(dr, k * 8 + k, 64);
+                    double sr = ok ? Pr[pk(kb + k, jj, n)] : 0.0;
+                    double si = ok ? Pi[pk(kb + k, jj, n)] : 0.0;
+#pragma unroll
+                    for (int l = 0; l < k; ++l) {
+                        // conj(R[l][k]) x_l
+                        const double ar = __shfl(dr, l * 8 + k, 64), ai = __shfl(di, l * 8 + k, 64);
+                        sr -= ar * xr[l] + ai * xi[l];
+                        si -= ar * xi[l] - ai * xr[l];
+                    }
+                    xr[k] = sr * dinv;
+                    xi[k] = si * dinv;
+                    if (ok) {
+                        Pr[pk(kb + k, jj, n)] = xr[k];
+                        Pi[pk(kb + k, jj, n)] = xi[k];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // trailing update of rows and columns >= kb + nb
+        for (int i = kb + nb + ty; i < n; i += 32) {
+            double ar[kCholBlk], ai[kCholBlk];
+#pragma unroll
+            for (int k = 0; k < kCholBlk; ++k) {
+                ar[k] = k < nb ? Pr[pk(kb + k, i, n)] : 0.0;
+                ai[k] = k < nb ? -Pi[pk(kb + k, i, n)] : 0.0;
+            }
+            const int ri = pk(i, i, n);
+            for (int j = i + tx; j < n; j += 32) {
+                double sr = Pr[ri + (j - i)], si = Pi[ri + (j - i)];
+#pragma unroll
+                for (int k = 0; k < kCholBlk; ++k) {
+                    if (k < nb) {
+                        const double br = Pr[pk(kb + k, j, n)], bi = Pi[pk(kb + k, j, n)];
+                        sr -= ar[k] * br - ai[k] * bi;
+                        si -= ar[k] * bi + ai[k] * br;
+                    }
+                }
+                Pr[ri + (j - i)] = sr;
+                Pi[ri + (j - i)] = si;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += kBlkThreads) {
+        const int i = e / n, j = e - i * n;
+        G[e] = (j >= i) ? Pr[pk(i, j, n)] : 0.0;
+        G[e + plane] = (j >= i) ? Pi[pk(i, j, n)] : 0.0;
+    }
+    __syncthreads();
+
+    // ----------------------------------------------------------- inverse
+    const int cc = tid & 7, ig = tid >> 3;   // 128 rows x 8 columns
+    for (int jb = 0; jb < n; jb += kCholBlk) {
+        const int nb = min(kCholBlk, n - jb);
+        // the last wavefront has no T rows (8 * jb <= 960): it inverts the
+        // diagonal block while the others form T
+        if (wave == kBlkThreads / 64 - 1 && lane < nb) {
+            // column c of the diagonal block's inverse, back substitution
+            const int c = lane;
+            double xr[kCholBlk], xi[kCholBlk];
+#pragma unroll
+            for (int r = kCholBlk - 1; r >= 0; --r) {
+                xr[r] = 0.0;
+                xi[r] = 0.0;
+                if (r == c) {
+                    xr[r] = 1.0 / Pr[pk(jb + r, jb + r, n)];
+                } else if (r < c) {
+                    double sr = 0.0, si = 0.0;
+#pragma unroll
+                    for (int k = r + 1; k < kCholBlk; ++k) {
+                        if (k <= c) {
+                            const double rr = Pr[pk(jb + r, jb + k, n)], ri = Pi[pk(jb + r, jb + k, n)];
+                            sr += rr * xr[k] - ri * xi[k];
+                            si += rr * xi[k] + ri * xr[k];
+                        }
+                    }
+                    const double inv = 1.0 / Pr[pk(jb + r, jb + r, n)];
+                    xr[r] = -sr * inv;
+                    xi[r] = -si * inv;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kCholBlk; ++r) {
+                xdr[r * kCholBlk + c] = xr[r];
+                xdi[r * kCholBlk + c] = xi[r];
+            }
+        }
+        // T[i][c] = sum_{i <= k < jb} X[i][k] R[k][jb + c], rows i < jb
+        for (int i = ig; i < jb; i += kBlkThreads / kCholBlk) {
+            if (cc < nb) {
+                double sr = 0.0, si = 0.0;
+                for (int k = i; k < jb; ++k) {
+                    const double xr_ = Pr[pk(i, k, n)], xi_ = Pi[pk(i, k, n)];
+                    const double rr = Pr[pk(k, jb + cc, n)], ri = Pi[pk(k, jb + cc, n)];
+                    sr += xr_ * rr - xi_ * ri;
+                    si += xr_ * ri + xi_ * rr;
+                }
+                Tr[i * kCholBlk + cc] = sr;
+                Ti[i * kCholBlk + cc] = si;
+            }
+        }
+        __syncthreads();   // diagonal inverse and T visible; column block J fully read
+        for (int i = ig; i < jb; i += kBlkThreads / kCholBlk) {
+            if (cc < nb) {
+                double ur = 0.0, ui = 0.0;
+#pragma unroll
+                for (int c = 0; c < kCholBlk; ++c) {
+                    if (c <= cc) {
+                        const double ar = Tr[i * kCholBlk + c], ai = Ti[i * kCholBlk + c];
+                        const double br = xdr[c * kCholBlk + cc], bi = xdi[c * kCholBlk + cc];
+                        ur += ar * br - ai * bi;
+                        ui += ar * bi + ai * br;
+                    }
+                }
+                Pr[pk(i, jb + cc, n)] = -ur;
+                Pi[pk(i, jb + cc, n)] = -ui;
+            }
+        }
+        if (tid < kCholBlk * kCholBlk) {
+            const int r = tid >> 3, c = tid & 7;
+            if (r <= c && c < nb) {
+                Pr[pk(jb + r, jb + c, n)] = xdr[r * kCholBlk + c];
+                Pi[pk(jb + r, jb + c, n)] = xdi[r * kCholBlk + c];
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += kBlkThreads) {
         const int i = e / n, j = e - i * n;
         X[e] = (j >= i) ? Pr[pk(i, j, n)] : 0.0;
         X[e + plane] = (j >= i) ? Pi[pk(i, j, n)] : 0.0;
@@ -311,6 +576,14 @@ static bool chol_lds_fits(Ctx* ctx, int64_t n) {
     FTD_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
     return sizeof(double) * (size_t)(n * (n + 1)) + 64 <= (size_t)lim;
 }
+static bool blk_fits(Ctx* ctx, int64_t n) {
+    int lim = 0;
+    FTD_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    // packed triangle, the T staging block and the kernel's static arrays
+    return sizeof(double) * (size_t)(n * (n + 1) + 2 * 128 * kCholBlk + 2 * kCholBlk * kCholBlk +
+                                     kBlkThreads / 64) <=
+           (size_t)lim;
+}
 static void chol_inv(Ctx* ctx, double* G, double* Xi, int64_t n, const double* shift, int* flag,
                      int* converged) {
     const int64_t nn = n * n;
@@ -320,7 +593,16 @@ static void chol_inv(Ctx* ctx, double* G, double* Xi, int64_t n, const double* s
         lds = hipFuncSetAttribute((const void*)chol_inv_lds_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
               hipSuccess;
-    if (lds) {
+    const size_t bbytes = bytes + sizeof(double) * 2 * 128 * kCholBlk;
+    bool blk = lds && n >= 16 && n <= 128 && blk_fits(ctx, n);
+    if (blk && bbytes > 48 * 1024)
+        blk = hipFuncSetAttribute((const void*)chol_inv_blk_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bbytes) ==
+              hipSuccess;
+    if (blk) {
+        chol_inv_blk_kernel<<<1, kBlkThreads, bbytes, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag,
+                                                                      ctx->kstop, converged);
+    } else if (lds) {
         chol_inv_lds_kernel<<<1, kCholThreads, bytes, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag,
                                                                      ctx->kstop, converged);
     } else {
