@@ -82,38 +82,38 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
     const Tin sa = p.conjA ? Tin(-1) : Tin(1);
     const Tin sb = p.conjB ? Tin(-1) : Tin(1);
 
-    // this thread's share of one k-tile: 4 (re, im) pairs of A and of B
+    // this thread's share of one k-tile: 4 (re, im) pairs of A and of B.
+    // Loads are unconditional from clamped (always valid) addresses, so the
+    // next tile's loads stay in flight during the MFMAs; out-of-range
+    // elements are zeroed, and the conjugation sign applied, when staging.
     Tin ra[4], ia[4], rb[4], ib[4];
+    unsigned inA = 0, inB = 0;   // bit i: element i lies inside the matrix
     auto fetch = [&](int g) {
         const int t = t0 + g / ktiles;
         const int k0 = (g % ktiles) * GBK;
         const Tin* Ab = A + p.term[t].offA;
         const Tin* Bb = B + p.term[t].offB;
+        inA = 0;
+        inB = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int mm = AK ? (tid >> 4) + 16 * i : (tid & 63);
             const int kk = AK ? (tid & 15) : (tid >> 6) + 4 * i;
             const int gm = m0 + mm, gk = k0 + kk;
-            ra[i] = 0;
-            ia[i] = 0;
-            if (gm < p.M && gk < p.K) {
-                const int64_t idx = (int64_t)gm * p.sAm + (int64_t)gk * p.sAk;
-                ra[i] = Ab[idx];
-                ia[i] = sa * Ab[idx + p.planeA];
-            }
+            inA |= (unsigned)(gm < p.M && gk < p.K) << i;
+            const int64_t idx = (int64_t)min(gm, p.M - 1) * p.sAm + (int64_t)min(gk, p.K - 1) * p.sAk;
+            ra[i] = Ab[idx];
+            ia[i] = Ab[idx + p.planeA];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int nn = BKC ? (tid >> 4) + 16 * i : (tid & 63);
             const int kk = BKC ? (tid & 15) : (tid >> 6) + 4 * i;
             const int gn = n0 + nn, gk = k0 + kk;
-            rb[i] = 0;
-            ib[i] = 0;
-            if (gn < p.N && gk < p.K) {
-                const int64_t idx = (int64_t)gk * p.sBk + (int64_t)gn * p.sBn;
-                rb[i] = Bb[idx];
-                ib[i] = sb * Bb[idx + p.planeB];
-            }
+            inB |= (unsigned)(gn < p.N && gk < p.K) << i;
+            const int64_t idx = (int64_t)min(gk, p.K - 1) * p.sBk + (int64_t)min(gn, p.N - 1) * p.sBn;
+            rb[i] = Bb[idx];
+            ib[i] = Bb[idx + p.planeB];
         }
     };
     auto stash = [&](int buf) {
@@ -121,15 +121,17 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
         for (int i = 0; i < 4; ++i) {
             const int mm = AK ? (tid >> 4) + 16 * i : (tid & 63);
             const int kk = AK ? (tid & 15) : (tid >> 6) + 4 * i;
-            As[buf][0][kk][mm] = ra[i];
-            As[buf][1][kk][mm] = ia[i];
+            const bool in = (inA >> i) & 1u;
+            As[buf][0][kk][mm] = in ? ra[i] : Tin(0);
+            As[buf][1][kk][mm] = in ? sa * ia[i] : Tin(0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int nn = BKC ? (tid >> 4) + 16 * i : (tid & 63);
             const int kk = BKC ? (tid & 15) : (tid >> 6) + 4 * i;
-            Bs[buf][0][kk][nn] = rb[i];
-            Bs[buf][1][kk][nn] = ib[i];
+            const bool in = (inB >> i) & 1u;
+            Bs[buf][0][kk][nn] = in ? rb[i] : Tin(0);
+            Bs[buf][1][kk][nn] = in ? sb * ib[i] : Tin(0);
         }
     };
 
