@@ -286,7 +286,9 @@ def main():
     t0 = time.perf_counter()
     phi0 = api.apply_compress(ctx, J, psi_beta, r.D, r.cutoff)
     t_j = time.perf_counter() - t0
-    log(f"[bench] j|Psi> compressed in {t_j:.1f} s")
+    pbonds = phi0.info()["bond_dims"]
+    log(f"[bench] j|Psi> compressed in {t_j:.1f} s, bonds max {max(pbonds)} "
+        f"mean {sum(pbonds) / len(pbonds):.1f}")
     psi0 = psi_beta
 
     # warmup (untimed), then the timed mixed-precision steps
@@ -320,8 +322,9 @@ def main():
         "config": {"workload": wl.name, "n_mol": m.n_mol, "local_modes": m.n_loc,
                    "bond_modes": m.n_nl, "levels": m.levels_loc, "D": r.D,
                    "T_K": 300.0, "dt_fs": 0.5, "krylov_tol": tol, "n_imag": r.n_imag,
-                   "n_grow": r.n_grow, "bond_max": max(bonds),
-                   "bond_mean": round(sum(bonds) / len(bonds), 1)},
+                   "n_grow": r.n_grow, "psi_bond_max": max(bonds),
+                   "psi_bond_mean": round(sum(bonds) / len(bonds), 1),
+                   "phi_bond_max": max(pbonds), "phi_bond_mean": round(sum(pbonds) / len(pbonds), 1)},
         "heff_tflops": st["heff_flops"] / max(st["heff_ms"], 1e-9) / 1e9,
         "matvecs_per_step": st["matvecs"] / args.steps,
         "krylov_mean": st["krylov_vectors"] / max(st["expm_calls"], 1),
