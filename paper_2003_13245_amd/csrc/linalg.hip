@@ -2,15 +2,17 @@
 //
 //  * qr_chol / lq_chol: shifted CholeskyQR in three passes for the gauge
 //    moves of the sweep (full-rank tall/wide blocks).  Every pass is a Gram
-//    GEMM, a one-workgroup Cholesky, a triangular inverse and an update
-//    GEMM; the R factors multiply to an upper factor with a real positive
-//    diagonal, i.e. the unique QR of a full-rank matrix.
+//    GEMM, a one-workgroup Cholesky and triangular inverse (blocked for
+//    16 <= n <= 128) and an update GEMM; the R factors multiply to an upper
+//    factor with a real positive diagonal, i.e. the unique QR of a full-rank
+//    matrix.
 //  * qr_householder: blocked Householder QR (compact WY) for matrices of any
 //    rank; used by the compressions, where MPO x MPS products are rank
 //    deficient.  Column-major working copy; panel columns are reflected with
 //    small reduction kernels, trailing columns with GEMMs.
 //  * svd_jacobi: one-sided (Hestenes) Jacobi with a round-robin pairing, one
-//    launch per round, every column pair in its own workgroup.
+//    cooperative launch per sweep with a grid barrier between rounds, every
+//    column pair on its own wavefront.
 #include <hip/hip_cooperative_groups.h>
 
 #include "common.h"
@@ -291,12 +293,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, d
 // per block of kCholBlk columns:
 //  factor, per block K: waves 0 and 1 factor the diagonal block in registers
 //    (lane = 8 r + c, pivots and rows exchanged by shuffles) and solve the
-//    block row R_KJ = R_KK^{-H} G_KJ, one column per lane; then every thread applies
-//    the rank-kCholBlk update G_JJ' -= R_KJ^H R_KJ' with its row's factors
-//    cached in registers;
+//    block row R_KJ = R_KK^{-H} G_KJ, one column per lane; then every thread
+//    applies the rank-kCholBlk update G_JJ' -= R_KJ^H R_KJ' with its row's
+//    factors cached in registers;
 //  invert in place, per block J: eight lanes of the last wave invert the
-//    diagonal block (one column each) while the other threads form T = X_{:,<J} R_{<J,J} for
-//    its (row, column) pair into LDS; after a barrier X_{<J,J} = -T X_JJ.
+//    diagonal block (one column each) while the other threads form
+//    T = X_{:,<J} R_{<J,J}, one (row, column) pair each, into LDS; after a
+//    barrier X_{<J,J} = -T X_JJ.
 // Dynamic LDS: the packed triangle plus 2 * 128 * kCholBlk doubles for T.
 constexpr int kCholBlk = 8;
 constexpr int kBlkThreads = 1024;
