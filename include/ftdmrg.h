@@ -273,6 +273,32 @@ ftd_status ftd_fgr_corr(const double* t, int32_t nt, const double* omega, const 
                         int32_t n_modes, double V, double beta, double e0, double R,
                         double* C_out);
 
+/* One point of a mobility sweep: inverse temperature beta = 1/(k_B T) (> 0),
+ * transfer integral V, and a frequency scale s > 0 applied to every mode
+ * (local and bond): omega -> s omega with g -> g / sqrt(s), which keeps each
+ * mode's reorganisation energy g^2 omega fixed.  s = sqrt(m/m') is an isotope
+ * substitution of mass m by m' (the isotope-effect passage), so the isotope
+ * effect mu'/mu - 1 is the ratio of two points that differ only in s. */
+typedef struct {
+    double beta;
+    double V;
+    double omega_scale;
+} ftd_sweep_point;
+
+/* Batched mobility runs (the temperature, coupling and isotope studies):
+ * for every point, the model `base` with V and the frequency scale of the
+ * point, its MPOs, Psi_beta (ftd_thermal_prep with n_imag, n_grow, D, cutoff,
+ * prec, ko), C(t_k) for k = 0..n_steps (ftd_corr_current with D, cutoff, dt,
+ * ko) and the Kubo mobility (ftd_mobility, e0 of the model).  mu_au and
+ * log_Z: host, n_pts doubles each.  The points run one after another on the
+ * context's streams; every intermediate is released before the next.
+ * Errors: those of the calls it makes, and FTD_EINVAL (n_pts < 1,
+ * n_steps < 1, beta <= 0, s <= 0, non-finite point). */
+ftd_status ftd_mobility_sweep(ftd_ctx* ctx, const ftd_model* base, const ftd_sweep_point* pts,
+                              int32_t n_pts, int32_t n_imag, int32_t n_grow, int32_t D,
+                              double cutoff, double dt, int32_t n_steps, ftd_precision prec,
+                              const ftd_krylov_opts* ko, double* mu_au, double* log_Z);
+
 /* Electronic reduced density matrix of a (purified) state, the phonon trace
  * of the coherent-length section: sigma = Tr_ph rho with rho = |psi><psi| /
  * <psi|psi> traced over the ancillas, i.e.

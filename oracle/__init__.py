@@ -13,7 +13,9 @@ Contents
   tdvp.py     purified MPS, imaginary-time preparation, one-site projector-
               splitting TDVP, the current correlation and the mobility
   analysis.py Kubo mobility, Fermi-golden-rule hopping-limit C(t), mean free
-              path
+              path, coherent length
+  sweep.py    batched mobility runs over temperature, transfer integral and
+              frequency scale (isotope substitution)
 
 Everything runs in float64 / complex128 with numpy and scipy.
 """

@@ -37,6 +37,10 @@ class KrylovOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("mmax", C.c_int32)]
 
 
+class SweepPoint(C.Structure):
+    _fields_ = [("beta", C.c_double), ("V", C.c_double), ("omega_scale", C.c_double)]
+
+
 class Stats(C.Structure):
     _fields_ = [("heff_launches", C.c_int64), ("heff_ms", C.c_double),
                 ("heff_flops", C.c_double), ("dom_launches", C.c_int64),
@@ -90,6 +94,7 @@ SIGNATURES = {
     "ftd_mobility": (I32, [DP, I32, D, D, D, DP, DP]),
     "ftd_mean_free_path": (I32, [DP, I32, D, D, DP, DP, DP]),
     "ftd_fgr_corr": (I32, [DP, I32, DP, DP, I32, D, D, D, D, DP]),
+    "ftd_mobility_sweep": (I32, [P, P, P, I32, I32, I32, I32, D, D, I32, I32, P, DP, DP]),
     "ftd_reduced_density": (I32, [P, P, P, DP]),
     "ftd_coherent_length": (I32, [DP, I32, DP]),
     "ftd_heff_apply": (I32, [P, P, P, I32, DP, DP, I32]),

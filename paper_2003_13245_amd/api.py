@@ -27,7 +27,7 @@ def _mark_shutdown():
 
 
 __all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_pair",
-           "corr_current", "mobility", "mean_free_path", "fgr_corr", "reduced_density",
+           "corr_current", "mobility", "mobility_sweep", "mean_free_path", "fgr_corr", "reduced_density",
            "coherent_length", "qr", "apply_compress", "overlap", "heff_apply", "mps_from_host",
            "gemm", "FtdError"]
 
@@ -276,6 +276,23 @@ def fgr_corr(t, V, omega, g, beta, e0=1.0, R=1.0):
                            int(om.size), float(V), float(beta), float(e0), float(R),
                            _abi._dptr(out)))
     return out[0::2] + 1j * out[1::2]
+
+
+def mobility_sweep(ctx, model, points, n_imag, n_grow, D, dt, n_steps, cutoff=1e-10,
+                   precision="c128", tol=1e-14, mmax=40):
+    """Mobility (a.u.) and ln Z for each (beta, V, omega_scale) point; the
+    frequency scale s maps omega -> s omega, g -> g / sqrt(s) on every mode."""
+    m, keep = _model_struct(model)
+    pts = (_abi.SweepPoint * len(points))(*[_abi.SweepPoint(float(b), float(v), float(sc))
+                                            for b, v, sc in points])
+    mu = np.zeros(len(points))
+    logz = np.zeros(len(points))
+    ko = _abi._krylov(tol, mmax)
+    check(lib.ftd_mobility_sweep(ctx.h, C.byref(m), pts, len(points), int(n_imag), int(n_grow),
+                                 int(D), float(cutoff), float(dt), int(n_steps),
+                                 PRECISION[precision], C.byref(ko), _abi._dptr(mu),
+                                 _abi._dptr(logz)))
+    return mu, logz
 
 
 def reduced_density(ctx, model, psi):

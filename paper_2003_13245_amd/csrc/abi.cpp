@@ -624,6 +624,69 @@ ftd_status ftd_mobility(const double* C, int32_t n, double dt, double beta, doub
     });
 }
 
+ftd_status ftd_mobility_sweep(ftd_ctx* ctx, const ftd_model* base, const ftd_sweep_point* pts,
+                              int32_t n_pts, int32_t n_imag, int32_t n_grow, int32_t D,
+                              double cutoff, double dt, int32_t n_steps, ftd_precision prec,
+                              const ftd_krylov_opts* ko, double* mu_au, double* log_Z) {
+    return guarded([&] {
+        FTD_CHECK(ctx && base && pts && mu_au && log_Z, FTD_EINVAL, "null argument");
+        FTD_CHECK(n_pts >= 1 && n_steps >= 1, FTD_EINVAL, "need n_pts >= 1 and n_steps >= 1");
+        check_model(base);
+        for (int p = 0; p < n_pts; ++p) {
+            const ftd_sweep_point& q = pts[p];
+            FTD_CHECK(std::isfinite(q.beta) && q.beta > 0.0 && std::isfinite(q.V) &&
+                          std::isfinite(q.omega_scale) && q.omega_scale > 0.0,
+                      FTD_EINVAL, "sweep point needs beta > 0, finite V and omega_scale > 0");
+        }
+        // the calls below report through the same thread-local message
+        auto call = [](ftd_status st) {
+            if (st != FTD_OK) throw Error{st, g_last_error};
+        };
+        for (int p = 0; p < n_pts; ++p) {
+            const ftd_sweep_point& q = pts[p];
+            const double s = q.omega_scale, r = 1.0 / std::sqrt(s);
+            std::vector<double> wl(base->n_loc), gl(base->n_loc), wn(base->n_nl), gn(base->n_nl);
+            for (int i = 0; i < base->n_loc; ++i) {
+                wl[i] = s * base->omega_loc[i];
+                gl[i] = r * base->g_loc[i];
+            }
+            for (int i = 0; i < base->n_nl; ++i) {
+                wn[i] = s * base->omega_nl[i];
+                gn[i] = r * base->g_nl[i];
+            }
+            ftd_model m = *base;
+            m.omega_loc = wl.data();
+            m.g_loc = gl.data();
+            m.omega_nl = wn.data();
+            m.g_nl = gn.data();
+            m.V = q.V;
+            ftd_mpo* H = nullptr;
+            ftd_mpo* J = nullptr;
+            ftd_mps* psi = nullptr;
+            std::vector<double> C(2 * ((size_t)n_steps + 1));
+            auto release = [&] {
+                if (psi) ftd_mps_destroy(psi);
+                if (J) ftd_mpo_destroy(J);
+                if (H) ftd_mpo_destroy(H);
+            };
+            try {
+                call(ftd_mpo_build(ctx, &m, &H, &J));
+                call(ftd_thermal_prep(ctx, H, q.beta, n_imag, n_grow, D, cutoff, prec, ko, &psi,
+                                      &log_Z[p]));
+                call(ftd_corr_current(ctx, H, J, psi, D, cutoff, dt, n_steps, ko, C.data()));
+                double mu_cm = 0.0;
+                call(ftd_mobility(C.data(), n_steps + 1, dt, q.beta, m.e0, &mu_au[p], &mu_cm));
+                vlog(&ctx->c, 1, "sweep point %d/%d: beta %.6g, V %.6g, s %.6g: mu %.9g a.u.", p + 1,
+                     n_pts, q.beta, q.V, s, mu_au[p]);
+            } catch (...) {
+                release();
+                throw;
+            }
+            release();
+        }
+    });
+}
+
 ftd_status ftd_reduced_density(ftd_ctx* ctx, const ftd_model* m, const ftd_mps* psi,
                                double* sigma) {
     return guarded([&] {
