@@ -299,6 +299,23 @@ ftd_status ftd_mobility_sweep(ftd_ctx* ctx, const ftd_model* base, const ftd_swe
                               double cutoff, double dt, int32_t n_steps, ftd_precision prec,
                               const ftd_krylov_opts* ko, double* mu_au, double* log_Z);
 
+/* Gradient of the mobility with respect to the shared mode parameters, by
+ * central finite differences through the whole GPU path (not the reverse-mode
+ * adjoint): mu of `model` at beta (runs as in ftd_mobility_sweep), and
+ * d mu / d omega_loc[k], d mu / d g_loc[k], d mu / d omega_nl[k],
+ * d mu / d g_nl[k], each (mu(x + h) - mu(x - h)) / 2h with h = rel_step |x|
+ * (rel_step itself for a parameter that is zero).  Cost: 1 + 4 (n_loc + n_nl)
+ * mobility runs.  The isotope derivative follows as
+ * d mu / d ln m = -1/2 sum_k omega_k d mu / d omega_k + 1/4 sum_k g_k d mu / d g_k.
+ * Gradient arrays: host, n_loc and n_nl doubles (may be null when the count
+ * is zero).  Errors: those of the runs, and FTD_EINVAL (beta <= 0,
+ * n_steps < 1, rel_step outside (0, 0.1)). */
+ftd_status ftd_mobility_grad(ftd_ctx* ctx, const ftd_model* model, double beta, int32_t n_imag,
+                             int32_t n_grow, int32_t D, double cutoff, double dt,
+                             int32_t n_steps, ftd_precision prec, const ftd_krylov_opts* ko,
+                             double rel_step, double* mu, double* dmu_domega_loc,
+                             double* dmu_dg_loc, double* dmu_domega_nl, double* dmu_dg_nl);
+
 /* Electronic reduced density matrix of a (purified) state, the phonon trace
  * of the coherent-length section: sigma = Tr_ph rho with rho = |psi><psi| /
  * <psi|psi> traced over the ancillas, i.e.

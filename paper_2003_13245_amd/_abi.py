@@ -95,6 +95,8 @@ SIGNATURES = {
     "ftd_mean_free_path": (I32, [DP, I32, D, D, DP, DP, DP]),
     "ftd_fgr_corr": (I32, [DP, I32, DP, DP, I32, D, D, D, D, DP]),
     "ftd_mobility_sweep": (I32, [P, P, P, I32, I32, I32, I32, D, D, I32, I32, P, DP, DP]),
+    "ftd_mobility_grad": (I32, [P, P, D, I32, I32, I32, D, D, I32, I32, P, D, DP, DP, DP, DP,
+                                DP]),
     "ftd_reduced_density": (I32, [P, P, P, DP]),
     "ftd_coherent_length": (I32, [DP, I32, DP]),
     "ftd_heff_apply": (I32, [P, P, P, I32, DP, DP, I32]),

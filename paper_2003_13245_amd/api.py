@@ -27,7 +27,7 @@ def _mark_shutdown():
 
 
 __all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_pair",
-           "corr_current", "mobility", "mobility_sweep", "mean_free_path", "fgr_corr", "reduced_density",
+           "corr_current", "mobility", "mobility_sweep", "mobility_grad", "mean_free_path", "fgr_corr", "reduced_density",
            "coherent_length", "qr", "apply_compress", "overlap", "heff_apply", "mps_from_host",
            "gemm", "FtdError"]
 
@@ -293,6 +293,26 @@ def mobility_sweep(ctx, model, points, n_imag, n_grow, D, dt, n_steps, cutoff=1e
                                  PRECISION[precision], C.byref(ko), _abi._dptr(mu),
                                  _abi._dptr(logz)))
     return mu, logz
+
+
+def mobility_grad(ctx, model, beta, n_imag, n_grow, D, dt, n_steps, cutoff=1e-10,
+                  precision="c128", tol=1e-14, mmax=40, rel_step=1e-4):
+    """(mu, gradients) with gradients a dict of d mu / d omega_loc, g_loc,
+    omega_nl, g_nl (arrays), by central finite differences on the GPU."""
+    m, keep = _model_struct(model)
+    nl, nn = len(model.omega_loc), len(model.omega_nl)
+    out = {k: np.zeros(max(1, n)) for k, n in (("omega_loc", nl), ("g_loc", nl),
+                                                  ("omega_nl", nn), ("g_nl", nn))}
+    mu = C.c_double()
+    ko = _abi._krylov(tol, mmax)
+    check(lib.ftd_mobility_grad(ctx.h, C.byref(m), float(beta), int(n_imag), int(n_grow), int(D),
+                                float(cutoff), float(dt), int(n_steps), PRECISION[precision],
+                                C.byref(ko), float(rel_step), C.byref(mu),
+                                _abi._dptr(out["omega_loc"]), _abi._dptr(out["g_loc"]),
+                                _abi._dptr(out["omega_nl"]), _abi._dptr(out["g_nl"])))
+    grads = {"omega_loc": out["omega_loc"][:nl], "g_loc": out["g_loc"][:nl],
+             "omega_nl": out["omega_nl"][:nn], "g_nl": out["g_nl"][:nn]}
+    return mu.value, grads
 
 
 def reduced_density(ctx, model, psi):

@@ -624,6 +624,39 @@ ftd_status ftd_mobility(const double* C, int32_t n, double dt, double beta, doub
     });
 }
 
+// the entry points below report through the same thread-local message
+static void call(ftd_status st) {
+    if (st != FTD_OK) throw Error{st, g_last_error};
+}
+
+// One mobility run of model m at beta: MPOs, Psi_beta, C(t), mu (a.u.).
+static double run_mobility(ftd_ctx* ctx, const ftd_model& m, double beta, int32_t n_imag,
+                           int32_t n_grow, int32_t D, double cutoff, double dt, int32_t n_steps,
+                           ftd_precision prec, const ftd_krylov_opts* ko, double* log_Z) {
+    ftd_mpo* H = nullptr;
+    ftd_mpo* J = nullptr;
+    ftd_mps* psi = nullptr;
+    std::vector<double> C(2 * ((size_t)n_steps + 1));
+    auto release = [&] {
+        if (psi) ftd_mps_destroy(psi);
+        if (J) ftd_mpo_destroy(J);
+        if (H) ftd_mpo_destroy(H);
+    };
+    double mu = 0.0, mu_cm = 0.0, lz = 0.0;
+    try {
+        call(ftd_mpo_build(ctx, &m, &H, &J));
+        call(ftd_thermal_prep(ctx, H, beta, n_imag, n_grow, D, cutoff, prec, ko, &psi, &lz));
+        call(ftd_corr_current(ctx, H, J, psi, D, cutoff, dt, n_steps, ko, C.data()));
+        call(ftd_mobility(C.data(), n_steps + 1, dt, beta, m.e0, &mu, &mu_cm));
+    } catch (...) {
+        release();
+        throw;
+    }
+    release();
+    if (log_Z) *log_Z = lz;
+    return mu;
+}
+
 ftd_status ftd_mobility_sweep(ftd_ctx* ctx, const ftd_model* base, const ftd_sweep_point* pts,
                               int32_t n_pts, int32_t n_imag, int32_t n_grow, int32_t D,
                               double cutoff, double dt, int32_t n_steps, ftd_precision prec,
@@ -638,10 +671,6 @@ ftd_status ftd_mobility_sweep(ftd_ctx* ctx, const ftd_model* base, const ftd_swe
                           std::isfinite(q.omega_scale) && q.omega_scale > 0.0,
                       FTD_EINVAL, "sweep point needs beta > 0, finite V and omega_scale > 0");
         }
-        // the calls below report through the same thread-local message
-        auto call = [](ftd_status st) {
-            if (st != FTD_OK) throw Error{st, g_last_error};
-        };
         for (int p = 0; p < n_pts; ++p) {
             const ftd_sweep_point& q = pts[p];
             const double s = q.omega_scale, r = 1.0 / std::sqrt(s);
@@ -660,29 +689,61 @@ ftd_status ftd_mobility_sweep(ftd_ctx* ctx, const ftd_model* base, const ftd_swe
             m.omega_nl = wn.data();
             m.g_nl = gn.data();
             m.V = q.V;
-            ftd_mpo* H = nullptr;
-            ftd_mpo* J = nullptr;
-            ftd_mps* psi = nullptr;
-            std::vector<double> C(2 * ((size_t)n_steps + 1));
-            auto release = [&] {
-                if (psi) ftd_mps_destroy(psi);
-                if (J) ftd_mpo_destroy(J);
-                if (H) ftd_mpo_destroy(H);
-            };
-            try {
-                call(ftd_mpo_build(ctx, &m, &H, &J));
-                call(ftd_thermal_prep(ctx, H, q.beta, n_imag, n_grow, D, cutoff, prec, ko, &psi,
-                                      &log_Z[p]));
-                call(ftd_corr_current(ctx, H, J, psi, D, cutoff, dt, n_steps, ko, C.data()));
-                double mu_cm = 0.0;
-                call(ftd_mobility(C.data(), n_steps + 1, dt, q.beta, m.e0, &mu_au[p], &mu_cm));
-                vlog(&ctx->c, 1, "sweep point %d/%d: beta %.6g, V %.6g, s %.6g: mu %.9g a.u.", p + 1,
-                     n_pts, q.beta, q.V, s, mu_au[p]);
-            } catch (...) {
-                release();
-                throw;
-            }
-            release();
+            mu_au[p] = run_mobility(ctx, m, q.beta, n_imag, n_grow, D, cutoff, dt, n_steps, prec,
+                                    ko, &log_Z[p]);
+            vlog(&ctx->c, 1, "sweep point %d/%d: beta %.6g, V %.6g, s %.6g: mu %.9g a.u.", p + 1,
+                 n_pts, q.beta, q.V, s, mu_au[p]);
+        }
+    });
+}
+
+ftd_status ftd_mobility_grad(ftd_ctx* ctx, const ftd_model* model, double beta, int32_t n_imag,
+                             int32_t n_grow, int32_t D, double cutoff, double dt,
+                             int32_t n_steps, ftd_precision prec, const ftd_krylov_opts* ko,
+                             double rel_step, double* mu, double* dmu_domega_loc,
+                             double* dmu_dg_loc, double* dmu_domega_nl, double* dmu_dg_nl) {
+    return guarded([&] {
+        FTD_CHECK(ctx && model && mu, FTD_EINVAL, "null argument");
+        FTD_CHECK(std::isfinite(beta) && beta > 0.0 && n_steps >= 1, FTD_EINVAL,
+                  "need beta > 0 and n_steps >= 1");
+        FTD_CHECK(std::isfinite(rel_step) && rel_step > 0.0 && rel_step < 0.1, FTD_EINVAL,
+                  "rel_step must lie in (0, 0.1)");
+        check_model(model);
+        FTD_CHECK((model->n_loc == 0 || (dmu_domega_loc && dmu_dg_loc)) &&
+                      (model->n_nl == 0 || (dmu_domega_nl && dmu_dg_nl)),
+                  FTD_EINVAL, "null gradient array");
+        std::vector<double> wl(model->omega_loc, model->omega_loc + model->n_loc);
+        std::vector<double> gl(model->g_loc, model->g_loc + model->n_loc);
+        std::vector<double> wn(model->omega_nl, model->omega_nl + model->n_nl);
+        std::vector<double> gn(model->g_nl, model->g_nl + model->n_nl);
+        ftd_model m = *model;
+        m.omega_loc = wl.data();
+        m.g_loc = gl.data();
+        m.omega_nl = wn.data();
+        m.g_nl = gn.data();
+        auto run = [&] {
+            return run_mobility(ctx, m, beta, n_imag, n_grow, D, cutoff, dt, n_steps, prec, ko,
+                                nullptr);
+        };
+        *mu = run();
+        // central difference in one parameter; step rel_step |x|, or rel_step
+        // itself for a parameter that is zero
+        auto central = [&](double& x) {
+            const double x0 = x, h = rel_step * (x0 != 0.0 ? std::fabs(x0) : 1.0);
+            x = x0 + h;
+            const double up = run();
+            x = x0 - h;
+            const double dn = run();
+            x = x0;
+            return (up - dn) / (2.0 * h);
+        };
+        for (int i = 0; i < model->n_loc; ++i) {
+            dmu_domega_loc[i] = central(wl[i]);
+            dmu_dg_loc[i] = central(gl[i]);
+        }
+        for (int i = 0; i < model->n_nl; ++i) {
+            dmu_domega_nl[i] = central(wn[i]);
+            dmu_dg_nl[i] = central(gn[i]);
         }
     });
 }

@@ -59,3 +59,21 @@ def test_uncoupled_ring_matches_closed_form_at_every_point():
         # Taylor-4 preparation and the projector-splitting drift at this
         # rank: measured 1.5e-7 to 1.3e-6 (a wrong beta, V or s is an O(1) error)
         assert abs(got - exact) <= 1e-5 * exact, (beta, V, s, got, exact)
+
+
+def test_gradient_chain_rule_matches_isotope_slope():
+    """The finite-difference gradient and the sweep probe mu along different
+    directions; the chain rule through omega -> s omega, g -> g/sqrt(s) ties
+    them: -1/2 d mu / d ln s at s = 1 equals -1/2 sum omega d mu/d omega +
+    1/4 sum g d mu/d g.  Both are central differences (error O(h^2) plus the
+    rounding of mu over h)."""
+    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=3)
+    run = dict(n_imag=6, n_grow=6, D=12, dt=0.1, n_steps=5)
+    mu, grads = S.mobility_grad(m, 1.0, rel_step=1e-4, **run)
+    assert mu == S.mobility_sweep(m, [(1.0, m.V, 1.0)], **run)[0][0]
+    iso = S.isotope_derivative(m, grads)
+    h = 1e-4
+    mus, _ = S.mobility_sweep(m, [(1.0, m.V, 1 + h), (1.0, m.V, 1 - h)], **run)
+    slope = -0.5 * (mus[0] - mus[1]) / (math.log(1 + h) - math.log(1 - h))
+    # measured 1.3e-9 relative
+    assert abs(slope - iso) <= 1e-6 * abs(iso), (slope, iso)
