@@ -179,6 +179,24 @@ ftd_status ftd_mps_from_host(ftd_ctx* ctx, int32_t n_sites, const int32_t* dims,
 ftd_status ftd_mps_set_precision(ftd_mps* psi, ftd_precision prec);
 /* <psi|psi> of the tensors (log_norm excluded), float64. */
 ftd_status ftd_mps_norm(ftd_ctx* ctx, const ftd_mps* psi, double* out);
+/* Overwrite site `site` of psi with host data of the same shape (count
+ * complex elements, interleaved, row-major [a][p][q][b]); the shape must be
+ * psi's (Dl, d, d, Dr) of that site.  For tests that plant a tensor.
+ * Errors: FTD_EINVAL (site out of range, count != Dl d d Dr, non-finite). */
+ftd_status ftd_mps_set_site(ftd_ctx* ctx, ftd_mps* psi, int32_t site, const double* host,
+                            int64_t count);
+/* Checkpoint and resume of a state, e.g. between two parts of a long C(t)
+ * run.  The file holds the exact float64 tensors, the log-norm factor and the
+ * contraction precision, so that continuing from a loaded state gives the
+ * same bits as not stopping.  Layout (little-endian): 8 bytes "FTDMPS01",
+ * int32 n_sites, int32 precision, double log_norm, int32 (Dl, d, d, Dr) per
+ * site, then per site the real plane and the imaginary plane of the tensor,
+ * each Dl*d*d*Dr doubles in [a][p][q][b] order.  save synchronises the
+ * context stream; load returns a new state owned by the caller.
+ * Errors: FTD_EINVAL (null path, file missing, short or malformed, bonds
+ * that do not chain), FTD_EDEVICE (write failure), FTD_ENOMEM. */
+ftd_status ftd_mps_save(ftd_ctx* ctx, const ftd_mps* psi, const char* path);
+ftd_status ftd_mps_load(ftd_ctx* ctx, const char* path, ftd_mps** out);
 
 /* ------------------------------------------------------- the hot path calls */
 
@@ -222,10 +240,13 @@ ftd_status ftd_apply_compress(ftd_ctx* ctx, const ftd_mpo* O, const ftd_mps* psi
                               double cutoff, ftd_mps** out);
 
 /* One propagation-and-compression stage of the bond growth:
- * out = compress(psi + c O phi, D) by zip-up (left-to-right SVD truncation
- * of the partial products to 2D, then a right-to-left sweep to D, keeping
- * s/s_max > cutoff).  psi and phi must carry the same log_norm; c is complex
- * (c[0] + i c[1]).  out belongs to the caller. */
+ * out = compress(psi + c O phi, D), the exact SVD compression of the sum
+ * (the same as ftd_apply_compress): the exact remainder right of every bond
+ * is factored right to left without forming the sum, then a left-to-right
+ * sweep keeps at most D singular values with s/s_max > cutoff per bond
+ * (whole near-degenerate multiplets), then an LQ sweep returns the state to
+ * right-canonical form.  psi and phi must carry the same log_norm; c is
+ * complex (c[0] + i c[1]).  out belongs to the caller. */
 ftd_status ftd_pc_stage(ftd_ctx* ctx, const ftd_mps* psi, const ftd_mpo* O, const ftd_mps* phi,
                         const double* c, int32_t D, double cutoff, ftd_mps** out);
 

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -17,19 +18,26 @@ from . import _abi
 from ._abi import FtdError, PRECISION, check, lib
 
 _SHUTDOWN = [False]
+_CONTEXTS = weakref.WeakSet()
 
 
 @atexit.register
-def _mark_shutdown():
-    # Native handles are released with the process; destroying them while the
-    # interpreter (and torch's allocator) tears down is not safe.
+def _release_all():
+    # Runs before torch's own exit handlers (this module is imported after
+    # torch): every live context is synchronised and destroyed together with
+    # its handles while the HIP runtime and torch's allocator are still up.
+    for ctx in list(_CONTEXTS):
+        try:
+            ctx.close()
+        except Exception:
+            pass
     _SHUTDOWN[0] = True
 
 
 __all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_pair",
            "corr_current", "mobility", "mobility_sweep", "mobility_grad", "mean_free_path", "fgr_corr", "reduced_density",
            "coherent_length", "qr", "apply_compress", "overlap", "heff_apply", "mps_from_host",
-           "gemm", "FtdError"]
+           "mps_load", "gemm", "FtdError"]
 
 
 class Context:
@@ -40,40 +48,66 @@ class Context:
     use_torch_allocator: route device allocations through torch's caching
     allocator."""
 
-    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = True,
+                 allocator=None):
+        """allocator: optional object with alloc(nbytes) -> device address
+        (0 on failure) and free(address), used instead of torch's caching
+        allocator (e.g. a pool, or a wrapper that counts or limits)."""
         self._alloc = None
         alloc_p = None
         if stream is None or use_torch_allocator:
             import torch
             if stream is None:
                 stream = torch.cuda.current_stream(device).cuda_stream
-            if use_torch_allocator:
-                dev = device
+        if allocator is not None:
+            def _a(nbytes, user):
+                try:
+                    return int(allocator.alloc(int(nbytes))) or None
+                except Exception:
+                    return None
 
-                def _a(nbytes, user):
-                    try:
-                        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self._stream)
-                    except Exception:
-                        return None
+            def _f(ptr, user):
+                allocator.free(ptr)
+        elif use_torch_allocator:
+            dev = device
 
-                def _f(ptr, user):
-                    torch.cuda.caching_allocator_delete(ptr)
+            def _a(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self._stream)
+                except Exception:
+                    return None
 
-                self._afn = _abi.ALLOC_FN(_a)
-                self._ffn = _abi.FREE_FN(_f)
-                self._alloc = _abi.Allocator(self._afn, self._ffn, None)
-                alloc_p = C.byref(self._alloc)
+            def _f(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+        if allocator is not None or use_torch_allocator:
+            self._afn = _abi.ALLOC_FN(_a)
+            self._ffn = _abi.FREE_FN(_f)
+            self._alloc = _abi.Allocator(self._afn, self._ffn, None)
+            alloc_p = C.byref(self._alloc)
         self._stream = int(stream)
         self.device = device
         h = C.c_void_p()
         check(lib.ftd_ctx_create(device, C.c_void_p(self._stream), alloc_p, C.byref(h)))
         self.h = h
+        self._handles = weakref.WeakSet()
+        _CONTEXTS.add(self)
+
+    def _track(self, handle):
+        self._handles.add(handle)
 
     def close(self):
-        """Release the context.  Handles created from it keep a reference to
-        this object, so the native context is destroyed only after the last of
-        them is gone."""
-        self._closed = True
+        """Synchronise and release the native context and every handle created
+        from it that is still alive (their later use raises).  Called for all
+        live contexts at interpreter exit."""
+        h = getattr(self, "h", None)
+        if not h:
+            return
+        lib.ftd_ctx_synchronize(h)
+        for obj in list(self._handles):
+            obj._release()
+        lib.ftd_ctx_destroy(h)
+        self.h = None
+        _CONTEXTS.discard(self)
 
     def __del__(self):
         try:
@@ -101,9 +135,29 @@ class Context:
         return {k: getattr(s, k) for k, _ in _abi.Stats._fields_}
 
 
-class Mpo:
+class _Handle:
+    _destroy = None
+
     def __init__(self, ctx, h):
         self.ctx, self.h = ctx, h
+        ctx._track(self)
+
+    def _release(self):
+        if self.h:
+            type(self)._destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.h and not _SHUTDOWN[0]:
+                type(self)._destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Mpo(_Handle):
+    _destroy = staticmethod(lib.ftd_mpo_destroy)
 
     def info(self):
         n = C.c_int32()
@@ -114,18 +168,9 @@ class Mpo:
                                w.ctypes.data_as(_abi.I32P)))
         return dims, w[: n.value - 1]
 
-    def __del__(self):
-        try:
-            if self.h and not _SHUTDOWN[0]:
-                lib.ftd_mpo_destroy(self.h)
-                self.h = None
-        except Exception:
-            pass
 
-
-class Mps:
-    def __init__(self, ctx, h):
-        self.ctx, self.h = ctx, h
+class Mps(_Handle):
+    _destroy = staticmethod(lib.ftd_mps_destroy)
 
     def info(self):
         n = C.c_int32()
@@ -157,13 +202,24 @@ class Mps:
         check(lib.ftd_mps_norm(self.ctx.h, self.h, C.byref(out)))
         return out.value
 
-    def __del__(self):
-        try:
-            if self.h and not _SHUTDOWN[0]:
-                lib.ftd_mps_destroy(self.h)
-                self.h = None
-        except Exception:
-            pass
+    def set_site(self, i: int, tensor):
+        """Overwrite site i with a host tensor of the same shape."""
+        t = np.ascontiguousarray(np.asarray(tensor, dtype=np.complex128)).reshape(-1)
+        buf = np.empty(2 * t.size)
+        buf[0::2] = t.real
+        buf[1::2] = t.imag
+        check(lib.ftd_mps_set_site(self.ctx.h, self.h, int(i), _abi._dptr(buf), t.size))
+
+    def save(self, path: str):
+        """Checkpoint the exact tensors, log-norm and precision to a file."""
+        check(lib.ftd_mps_save(self.ctx.h, self.h, str(path).encode()))
+
+
+def mps_load(ctx, path):
+    """A state written by Mps.save."""
+    out = C.c_void_p()
+    check(lib.ftd_mps_load(ctx.h, str(path).encode(), C.byref(out)))
+    return Mps(ctx, out)
 
 
 def _model_struct(model):

@@ -383,6 +383,122 @@ ftd_status ftd_mps_from_host(ftd_ctx* ctx, int32_t n_sites, const int32_t* dims,
     });
 }
 
+ftd_status ftd_mps_set_site(ftd_ctx* ctx, ftd_mps* psi, int32_t site, const double* host,
+                            int64_t count) {
+    return guarded([&] {
+        FTD_CHECK(ctx && psi && host, FTD_EINVAL, "null argument");
+        Mps* m = psi->m;
+        FTD_CHECK(site >= 0 && site < m->L, FTD_EINVAL, "site out of range");
+        const int64_t n = m->size(site);
+        FTD_CHECK(count == n, FTD_EINVAL, "element count differs from the site's shape");
+        std::vector<double> tmp(2 * n);
+        for (int64_t k = 0; k < n; ++k) {
+            FTD_CHECK(std::isfinite(host[2 * k]) && std::isfinite(host[2 * k + 1]), FTD_EINVAL,
+                      "non-finite tensor element");
+            tmp[k] = host[2 * k];
+            tmp[k + n] = host[2 * k + 1];
+        }
+        FTD_HIP(hipMemcpyAsync(m->A[site], tmp.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice,
+                               ctx->c.stream));
+        FTD_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+static const char kMpsMagic[8] = {'F', 'T', 'D', 'M', 'P', 'S', '0', '1'};
+
+ftd_status ftd_mps_save(ftd_ctx* ctx, const ftd_mps* psi, const char* path) {
+    return guarded([&] {
+        FTD_CHECK(ctx && psi && path, FTD_EINVAL, "null argument");
+        const Mps* m = psi->m;
+        FILE* f = std::fopen(path, "wb");
+        FTD_CHECK(f != nullptr, FTD_EINVAL, std::string("cannot open for writing: ") + path);
+        bool ok = true;
+        auto put = [&](const void* p, size_t n) { ok = ok && std::fwrite(p, 1, n, f) == n; };
+        try {
+            put(kMpsMagic, 8);
+            const int32_t L = m->L, prec = (int32_t)m->prec;
+            put(&L, 4);
+            put(&prec, 4);
+            put(&m->log_norm, 8);
+            for (int i = 0; i < L; ++i) {
+                const int32_t dims[4] = {m->Dl[i], m->d[i], m->d[i], m->Dr[i]};
+                put(dims, sizeof(dims));
+            }
+            std::vector<double> tmp;
+            for (int i = 0; i < L && ok; ++i) {
+                const int64_t n = m->size(i);
+                tmp.resize(2 * n);
+                FTD_HIP(hipMemcpyAsync(tmp.data(), m->A[i], sizeof(double) * 2 * n,
+                                       hipMemcpyDeviceToHost, ctx->c.stream));
+                FTD_HIP(hipStreamSynchronize(ctx->c.stream));
+                put(tmp.data(), sizeof(double) * 2 * n);
+            }
+        } catch (...) {
+            std::fclose(f);
+            throw;
+        }
+        ok = (std::fclose(f) == 0) && ok;
+        FTD_CHECK(ok, FTD_EDEVICE, std::string("write failed: ") + path);
+    });
+}
+
+ftd_status ftd_mps_load(ftd_ctx* ctx, const char* path, ftd_mps** out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && path && out, FTD_EINVAL, "null argument");
+        FILE* f = std::fopen(path, "rb");
+        FTD_CHECK(f != nullptr, FTD_EINVAL, std::string("cannot open: ") + path);
+        Mps* m = nullptr;
+        auto get = [&](void* p, size_t n) {
+            FTD_CHECK(std::fread(p, 1, n, f) == n, FTD_EINVAL, "state file is short");
+        };
+        try {
+            char magic[8];
+            get(magic, 8);
+            FTD_CHECK(std::memcmp(magic, kMpsMagic, 8) == 0, FTD_EINVAL, "not a state file");
+            int32_t L = 0, prec = 0;
+            double log_norm = 0.0;
+            get(&L, 4);
+            get(&prec, 4);
+            get(&log_norm, 8);
+            FTD_CHECK(L >= 1 && L <= (1 << 20), FTD_EINVAL, "bad site count in state file");
+            FTD_CHECK(prec == FTD_C128 || prec == FTD_C64, FTD_EINVAL, "bad precision in state file");
+            FTD_CHECK(std::isfinite(log_norm), FTD_EINVAL, "non-finite log norm in state file");
+            std::vector<int> Dl(L), d(L), Dr(L);
+            for (int i = 0; i < L; ++i) {
+                int32_t dims[4];
+                get(dims, sizeof(dims));
+                FTD_CHECK(dims[0] >= 1 && dims[1] >= 1 && dims[1] == dims[2] && dims[3] >= 1 &&
+                              dims[0] <= (1 << 16) && dims[1] <= 64 && dims[3] <= (1 << 16),
+                          FTD_EINVAL, "bad site shape in state file");
+                Dl[i] = dims[0];
+                d[i] = dims[1];
+                Dr[i] = dims[3];
+                if (i > 0) FTD_CHECK(Dl[i] == Dr[i - 1], FTD_EINVAL, "bonds do not chain");
+            }
+            FTD_CHECK(Dl[0] == 1 && Dr[L - 1] == 1, FTD_EINVAL, "open boundary bonds must be 1");
+            m = mps_alloc(&ctx->c, Dl, d, Dr, static_cast<Prec>(prec));
+            std::vector<double> tmp;
+            for (int i = 0; i < L; ++i) {
+                const int64_t n = m->size(i);
+                tmp.resize(2 * n);
+                get(tmp.data(), sizeof(double) * 2 * n);
+                FTD_HIP(hipMemcpyAsync(m->A[i], tmp.data(), sizeof(double) * 2 * n,
+                                       hipMemcpyHostToDevice, ctx->c.stream));
+                FTD_HIP(hipStreamSynchronize(ctx->c.stream));
+            }
+            char extra;
+            FTD_CHECK(std::fread(&extra, 1, 1, f) == 0, FTD_EINVAL, "trailing bytes in state file");
+            m->log_norm = log_norm;
+        } catch (...) {
+            std::fclose(f);
+            mps_free(m);
+            throw;
+        }
+        std::fclose(f);
+        *out = new ftd_mps{m};
+    });
+}
+
 ftd_status ftd_mps_set_precision(ftd_mps* psi, ftd_precision prec) {
     return guarded([&] {
         FTD_CHECK(psi, FTD_EINVAL, "null argument");

@@ -189,6 +189,8 @@ void qr_chol(Ctx* ctx, double* M, int64_t m, int64_t n, double* R, bool check = 
 void lq_chol(Ctx* ctx, double* M, int64_t n, int64_t m, double* L, bool check = true);
 // reads and clears the sticky CholeskyQR breakdown flag; throws if it was set
 void chol_flag_check(Ctx* ctx);
+// clears that flag (after a failed sweep, whose gauge moves may have set it)
+void chol_flag_clear(Ctx* ctx);
 // Householder QR for any rank of an m x n matrix A: Q (m x r, row-major, not
 // formed when Q is null) and R (r x n, row-major), r = min(m, n), diag(R)
 // real >= 0.  A = M (row-major m x n), or A = M^H for a row-major n x m M

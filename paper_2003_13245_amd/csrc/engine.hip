@@ -813,7 +813,23 @@ static void absorb_left(Ctx* ctx, Mps* psi, int i, const double* C) {
 }
 
 // ============================================================ TDVP sweep
+static void tdvp_sweeps(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax);
+
 void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
+    try {
+        tdvp_sweeps(ctx, H, psi, z, tol, mmax);
+    } catch (...) {
+        // a failed sweep may leave the sticky breakdown flag set by gauge
+        // moves it had already queued: clear it for the next call
+        try {
+            chol_flag_clear(ctx);
+        } catch (...) {
+        }
+        throw;
+    }
+}
+
+static void tdvp_sweeps(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
     const int L = psi->L;
     FTD_CHECK(H->L == L, FTD_EINVAL, "MPO and MPS lengths differ");
     const Prec prec = psi->prec;

@@ -627,6 +627,11 @@ void chol_flag_check(Ctx* ctx) {
     }
 }
 
+void chol_flag_clear(Ctx* ctx) {
+    set_int_kernel<<<1, 1, 0, ctx->stream>>>(ctx->iscal + 8, 0);
+    FTD_HIP(hipGetLastError());
+}
+
 // The breakdown flag is sticky: kernels only set it; chol_flag_check reads
 // and clears it (at once when `check`, else left to the caller).
 static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout, bool wide,

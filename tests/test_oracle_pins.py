@@ -184,6 +184,54 @@ def test_compress_without_truncation_is_exact():
     assert np.abs(T.to_dense(Y) - T.to_dense(X)).max() < 1e-13
 
 
+def _schmidt_state(rng, s, dims, cut):
+    """Dense purified vector sum_i s_i |L_i>|R_i> with orthonormal L_i on
+    sites < cut and R_i on sites >= cut (random unitaries), as an exact MPS
+    whose every bond is then put in a random non-canonical gauge (A_i G,
+    G^-1 A_{i+1}), so nothing about the tensors is orthonormal."""
+    nl = int(np.prod([d * d for d in dims[:cut]]))
+    nr = int(np.prod([d * d for d in dims[cut:]]))
+
+    def unitary(n):
+        q, r = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+        return q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+
+    U, V = unitary(nl), unitary(nr)
+    k = len(s)
+    vec = (U[:, :k] * s[None, :]) @ V[:, :k].T
+    psi = T.full_rank_mps(vec.reshape(-1), dims)
+    for i in range(len(dims) - 1):
+        b = psi.A[i].shape[3]
+        G = np.eye(b) + 0.5 * (rng.standard_normal((b, b)) + 1j * rng.standard_normal((b, b)))
+        psi.A[i] = np.tensordot(psi.A[i], G, axes=([3], [0]))
+        psi.A[i + 1] = np.tensordot(np.linalg.inv(G), psi.A[i + 1], axes=([1], [0]))
+    return vec.reshape(-1), psi
+
+
+@pytest.mark.parametrize("k", [4, 6, 11])
+def test_truncated_compression_is_eckart_young_optimal(k):
+    """Truncating one Schmidt cut of a state with known Schmidt values s_i to
+    k values is, by the Eckart-Young theorem, the best rank-k approximation:
+    the residual is ||psi - psi_k||^2 = sum_{i>k} s_i^2 and the overlap
+    <psi|psi_k> = |psi_k|^2 = sum_{i<=k} s_i^2, whatever gauge the input
+    tensors are in.  Four sites of d = 2 (bonds 4, 16, 4); the middle cut
+    carries 16 distinct Schmidt values and is the only bond truncated (the
+    outer bonds have rank 4 <= k)."""
+    rng = np.random.default_rng(17)
+    dims = [2, 2, 2, 2]
+    s = np.sort(np.exp(-0.45 * np.arange(16)) * (1 + 0.05 * rng.uniform(size=16)))[::-1]
+    s = s / np.linalg.norm(s)
+    v, psi = _schmidt_state(rng, s, dims, 2)
+    assert np.abs(T.to_dense(psi) - v).max() < 1e-12
+    out = T.compress(psi, k, 1e-10)
+    assert out.bond_dims() == [4, k, 4]
+    w = T.to_dense(out)
+    tail, head = float(np.sum(s[k:] ** 2)), float(np.sum(s[:k] ** 2))
+    assert abs(np.linalg.norm(v - w) ** 2 - tail) < 1e-13
+    assert abs(np.vdot(v, w) - head) < 1e-13
+    assert abs(np.linalg.norm(w) ** 2 - head) < 1e-13
+
+
 def test_mps_add_and_taylor_growth_against_dense():
     """One growth step equals the fourth-order Taylor polynomial of
     exp(-dtau H) applied to |I> when nothing is truncated."""
