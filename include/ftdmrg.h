@@ -98,7 +98,11 @@ typedef struct {
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device`.  `hip_stream` is a borrowed
- * hipStream_t (NULL = the null stream).  `alloc` may be NULL (hipMalloc). */
+ * hipStream_t (NULL = the null stream).  `alloc` may be NULL (hipMalloc).
+ * ftd_ctx_destroy synchronises the stream and gives up the caller's
+ * reference: every MPO and MPS handle made on the context holds one too, so
+ * the context's memory is released when the last of them is destroyed, in
+ * whatever order (the context itself may not be used after destroy). */
 ftd_status ftd_ctx_create(int32_t device, void* hip_stream, const ftd_allocator* alloc,
                           ftd_ctx** out);
 void ftd_ctx_destroy(ftd_ctx* ctx);

@@ -69,11 +69,11 @@ class Context:
             def _f(ptr, user):
                 allocator.free(ptr)
         elif use_torch_allocator:
-            dev = device
+            dev, st = device, int(stream)
 
             def _a(nbytes, user):
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self._stream)
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
                 except Exception:
                     return None
 

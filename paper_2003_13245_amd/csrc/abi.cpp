@@ -93,6 +93,33 @@ static Ctx* aux_ctx(ftd_ctx* ctx) {
     return a;
 }
 
+static void ctx_free(ftd_ctx* ctx) {
+    if (ctx->aux) {
+        ctx_release(*ctx->aux);
+        (void)hipStreamDestroy(ctx->aux->stream);
+        delete ctx->aux;
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    ctx_release(ctx->c);
+    delete ctx;
+}
+
+// drop one reference to the context a handle was made on
+static void ctx_unref(Ctx* c) {
+    if (c->refs.fetch_sub(1) == 1) ctx_free(static_cast<ftd_ctx*>(c->owner));
+}
+
+static ftd_mps* mps_handle(Mps* m) {
+    m->ctx->refs.fetch_add(1);
+    return new ftd_mps{m};
+}
+
+static ftd_mpo* mpo_handle(Mpo* m) {
+    m->ctx->refs.fetch_add(1);
+    return new ftd_mpo{m};
+}
+
 extern "C" {
 
 const char* ftd_last_error(void) { return g_last_error.c_str(); }
@@ -106,6 +133,7 @@ ftd_status ftd_ctx_create(int32_t device, void* hip_stream, const ftd_allocator*
         FTD_CHECK(device >= 0 && device < n, FTD_EINVAL, "device index out of range");
         FTD_HIP(hipSetDevice(device));
         ftd_ctx* h = new ftd_ctx();
+        h->c.owner = h;
         try {
             ctx_init(h->c, device, static_cast<hipStream_t>(hip_stream), alloc);
         } catch (...) {
@@ -119,15 +147,8 @@ ftd_status ftd_ctx_create(int32_t device, void* hip_stream, const ftd_allocator*
 
 void ftd_ctx_destroy(ftd_ctx* ctx) {
     if (!ctx) return;
-    if (ctx->aux) {
-        ctx_release(*ctx->aux);
-        (void)hipStreamDestroy(ctx->aux->stream);
-        delete ctx->aux;
-    }
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
-    ctx_release(ctx->c);
-    delete ctx;
+    (void)hipStreamSynchronize(ctx->c.stream);
+    ctx_unref(&ctx->c);
 }
 
 ftd_status ftd_ctx_set_timing(ftd_ctx* ctx, int32_t enable) {
@@ -281,16 +302,18 @@ ftd_status ftd_mpo_build(ftd_ctx* ctx, const ftd_model* m, ftd_mpo** H, ftd_mpo*
             destroy_mpo(j);
             throw;
         }
-        *H = new ftd_mpo{h};
-        *J = new ftd_mpo{j};
+        *H = mpo_handle(h);
+        *J = mpo_handle(j);
     });
 }
 
 void ftd_mpo_destroy(ftd_mpo* mpo) {
     if (!mpo) return;
-    (void)hipStreamSynchronize(mpo->m->ctx->stream);
+    Ctx* c = mpo->m->ctx;
+    (void)hipStreamSynchronize(c->stream);
     destroy_mpo(mpo->m);
     delete mpo;
+    ctx_unref(c);
 }
 
 ftd_status ftd_mpo_info(const ftd_mpo* mpo, int32_t* n_sites, int32_t* dims, int32_t* bond_w) {
@@ -306,15 +329,17 @@ ftd_status ftd_mpo_info(const ftd_mpo* mpo, int32_t* n_sites, int32_t* dims, int
 
 void ftd_mps_destroy(ftd_mps* psi) {
     if (!psi) return;
-    (void)hipStreamSynchronize(psi->m->ctx->stream);
+    Ctx* c = psi->m->ctx;
+    (void)hipStreamSynchronize(c->stream);
     mps_free(psi->m);
     delete psi;
+    ctx_unref(c);
 }
 
 ftd_status ftd_mps_copy(ftd_ctx* ctx, const ftd_mps* src, ftd_mps** out) {
     return guarded([&] {
         FTD_CHECK(ctx && src && out, FTD_EINVAL, "null argument");
-        *out = new ftd_mps{mps_clone(src->m)};
+        *out = mps_handle(mps_clone(src->m));
     });
 }
 
@@ -379,7 +404,7 @@ ftd_status ftd_mps_from_host(ftd_ctx* ctx, int32_t n_sites, const int32_t* dims,
             off += n;
         }
         m->log_norm = log_norm;
-        *out = new ftd_mps{m};
+        *out = mps_handle(m);
     });
 }
 
@@ -495,7 +520,7 @@ ftd_status ftd_mps_load(ftd_ctx* ctx, const char* path, ftd_mps** out) {
             throw;
         }
         std::fclose(f);
-        *out = new ftd_mps{m};
+        *out = mps_handle(m);
     });
 }
 
@@ -614,7 +639,7 @@ ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t
             throw;
         }
         *log_Z = 2.0 * psi->log_norm;
-        *psi_beta = new ftd_mps{psi};
+        *psi_beta = mps_handle(psi);
     });
 }
 
@@ -656,7 +681,7 @@ ftd_status ftd_apply_compress(ftd_ctx* ctx, const ftd_mpo* O, const ftd_mps* psi
         FTD_CHECK(O->m->L == psi->m->L, FTD_EINVAL, "MPO and MPS lengths differ");
         Mps* r = apply_compress(&ctx->c, O->m, psi->m, D, cutoff);
         r->prec = psi->m->prec;
-        *out = new ftd_mps{r};
+        *out = mps_handle(r);
     });
 }
 
@@ -666,7 +691,7 @@ ftd_status ftd_pc_stage(ftd_ctx* ctx, const ftd_mps* psi, const ftd_mpo* O, cons
         FTD_CHECK(ctx && psi && O && phi && c && out, FTD_EINVAL, "null argument");
         FTD_CHECK(D >= 1, FTD_EINVAL, "D must be >= 1");
         Mps* r = pc_stage(&ctx->c, psi->m, O->m, phi->m, cplx(c[0], c[1]), D, cutoff);
-        *out = new ftd_mps{r};
+        *out = mps_handle(r);
     });
 }
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <atomic>
 #include <complex>
 #include <cstdint>
 #include <cstring>
@@ -244,6 +245,12 @@ struct EventPair {
 };
 
 struct Ctx {
+    // Lifetime across the ABI: every ftd_mps / ftd_mpo handle made on this
+    // context holds a reference, and so does the ftd_ctx handle until
+    // ftd_ctx_destroy; the context is released when the last one goes, so
+    // handles may be destroyed before or after their context.
+    std::atomic<int> refs{1};
+    void* owner = nullptr;   // the ftd_ctx this context belongs to
     int device = 0;
     hipStream_t stream = nullptr;
     bool has_alloc = false;

@@ -192,3 +192,23 @@ def test_non_finite_state_and_short_krylov_space(ctx):
     good = api.mps_from_host(ctx, random_mps(dims, 6, rng, 0).A)
     api.tdvp_step(ctx, H, good, dt_real=0.1)
     assert abs(good.norm2() - 1.0) < 1e-12
+
+
+def test_handles_may_outlive_their_context():
+    """ftd_ctx_destroy before the handles made on the context: the context
+    stays alive until the last handle is destroyed (no use after free), in
+    either order of handle destruction."""
+    import gc
+    from paper_2003_13245_amd import _abi, api
+    for order in (0, 1):
+        c = api.Context(0)
+        m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2)
+        H, J = api.mpo_build(c, m)
+        psi, _ = api.thermal_prep(c, H, 1.0, 4, 1, 6)
+        _abi.lib.ftd_ctx_destroy(c.h)
+        c.h = None
+        objs = [H, J, psi] if order == 0 else [psi, J, H]
+        for o in objs:
+            o._release()
+        del objs, H, J, psi, c
+        gc.collect()
