@@ -402,6 +402,27 @@ ftd_status ftd_svd_trunc(ftd_ctx* ctx, int32_t M, int32_t N, const double* T, in
 ftd_status ftd_gemm(ftd_ctx* ctx, int32_t precision, int32_t M, int32_t N, int32_t K,
                     int32_t transA, int32_t transB, const double* A, const double* B, double* C);
 
+/* ftd_gemm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product C = op(A) op(B) by the same kernels, on device buffers, with
+ * no allocation of any kind.  A, B, C: device memory of the context's GPU in
+ * split planes (the whole real plane, then the whole imaginary plane), each
+ * plane row-major as in ftd_gemm: A is M x K (trans 0) or K x M (trans 1, 2),
+ * B is K x N (0) or N x K (1, 2); element type double for FTD_C128, float for
+ * FTD_C64; C is M x N double (both precisions).  Buffers stay owned by the
+ * caller.  The split-K partial sums go to a fixed 32 MiB device array that
+ * the library holds on every GPU it has run on until the process ends, so M*N
+ * is limited to 2^20 output elements (larger requests: FTD_EINVAL, nothing
+ * enqueued); when the split count ftd_gemm would use does not fit, fewer
+ * splits are used.  Asynchronous on the context stream (no synchronisation).
+ * Every call on one GPU shares that array, which keeps the last call's
+ * contents: calls that overlap on one GPU (two streams, two contexts, two
+ * host threads) race and must be ordered by the caller.  Errors: FTD_EINVAL
+ * (null, sizes, trans, precision), FTD_EDEVICE (launch failure). */
+ftd_status ftd_gemm_noalloc(ftd_ctx* ctx, int32_t precision, int32_t M, int32_t N, int32_t K,
+                            int32_t transA, int32_t transB, const void* A, const void* B,
+                            double* C);
+
 #ifdef __cplusplus
 }
 #endif

@@ -106,6 +106,7 @@ SIGNATURES = {
     "ftd_svd_trunc": (I32, [P, I32, I32, DP, I32, D, I32, DP, DP, I32P]),
     "ftd_qr": (I32, [P, I32, I32, DP, I32, DP, DP]),
     "ftd_gemm": (I32, [P, I32, I32, I32, I32, I32, I32, DP, DP, DP]),
+    "ftd_gemm_noalloc": (I32, [P, I32, I32, I32, I32, I32, I32, P, P, P]),
 }
 
 

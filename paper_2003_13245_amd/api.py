@@ -445,6 +445,24 @@ def gemm(ctx, A, B, transA=0, transB=0, precision="c128"):
     return (cb[0::2] + 1j * cb[1::2]).reshape(M, N)
 
 
+def gemm_noalloc(ctx, A, B, C_out, M, N, K, transA=0, transB=0, precision="c128"):
+    """ftd_gemm_noalloc on device tensors in split planes (real plane, then
+    imaginary plane): A and B float64 (c128) or float32 (c64), C_out float64
+    with 2*M*N elements.  Enqueued on the context stream; nothing is
+    allocated."""
+    import torch
+    et = torch.float64 if precision == "c128" else torch.float32
+    na = M * K
+    nb = K * N
+    for name, t, n, dt in (("A", A, 2 * na, et), ("B", B, 2 * nb, et),
+                           ("C_out", C_out, 2 * M * N, torch.float64)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"{name}: need a contiguous {dt} device tensor of {n} elements")
+    check(lib.ftd_gemm_noalloc(ctx.h, PRECISION[precision], int(M), int(N), int(K),
+                               int(transA), int(transB), C.c_void_p(A.data_ptr()),
+                               C.c_void_p(B.data_ptr()), C.c_void_p(C_out.data_ptr())))
+
+
 def svd_trunc(ctx, T, D, cutoff=1e-10, s_left=True):
     """Truncated SVD on the device: returns (L, R) with T ~ L @ R."""
     T = np.ascontiguousarray(np.asarray(T, dtype=np.complex128))

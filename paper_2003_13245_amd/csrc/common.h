@@ -106,6 +106,14 @@ enum KernelTag { TAG_NONE = 0, TAG_HEFF = 1, TAG_KEFF = 2 };
 // Launch a complex GEMM.  Tin/Tout: double/double, float/float, float/double.
 void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void* C,
           GemmParams p, int tag);
+// The same kernels with caller-provided split-K partial storage (partial_cap
+// bytes; fewer splits are used when the chosen count does not fit), no
+// allocation and no timing.
+void gemm_in(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void* C,
+             GemmParams p, void* partial, size_t partial_cap);
+// Device address of this library's static scratch array on `device`, looked
+// up once per device (the device must be current).
+void scratch_init(int device);
 
 // ---------------------------------------------------------- channel mixing
 // out_j[a][p'][q][b] (+)= sum_e op_e[p'][p] in_e[a][p][q][b]

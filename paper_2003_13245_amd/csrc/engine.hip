@@ -58,6 +58,7 @@ void DBuf::release(Ctx* ctx) {
 void ctx_init(Ctx& c, int device, hipStream_t stream, const ftd_allocator* alloc) {
     c.device = device;
     c.stream = stream;
+    scratch_init(device);
     if (alloc && alloc->alloc && alloc->free) {
         c.has_alloc = true;
         c.alloc = *alloc;

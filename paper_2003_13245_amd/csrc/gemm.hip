@@ -261,16 +261,14 @@ static void launch(Ctx* ctx, const void* A, const void* B, void* C, const GemmPa
     }
 }
 
-void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void* C,
-          GemmParams p, int tag) {
-    FTD_CHECK(p.nprob >= 1 && p.nprob <= kMaxProbs, FTD_EINVAL, "gemm: bad problem count");
-    if (p.M <= 0 || p.N <= 0) return;
+// Number of k-splits of a launch: when the output tiles alone give fewer
+// than 512 workgroups and there is enough depth, the summed k range is split
+// so that about 1024 workgroups run, each over at least 4 k-tiles (at most
+// 64 splits).  Returns 0 for a launch with nothing to compute.
+static int split_count(const GemmParams& p) {
     int nterms = 0;
     for (int i = 0; i < p.nprob; ++i) nterms = std::max(nterms, p.prob[i].t1 - p.prob[i].t0);
-    if (p.K <= 0 || nterms == 0) {
-        FTD_CHECK(p.accumulate, FTD_EINVAL, "gemm: empty contraction without accumulate");
-        return;
-    }
+    if (p.K <= 0 || nterms == 0) return 0;
     const int tm = (p.M + GBM - 1) / GBM, tn = (p.N + GBN - 1) / GBN;
     const int ktiles = nterms * ((p.K + GBK - 1) / GBK);
     const int blocks = tm * tn * p.nprob;
@@ -281,13 +279,55 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
         ks = std::min(ks, 64);
         ks = std::max(ks, 1);
     }
+    return ks;
+}
+
+static size_t partial_bytes(const GemmParams& p, int ks, size_t esz) {
+    return ks > 1 ? 2 * (size_t)ks * p.nprob * (size_t)p.M * p.N * esz : 0;
+}
+
+void gemm_in(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void* C,
+             GemmParams p, void* partial, size_t partial_cap) {
+    FTD_CHECK(p.nprob >= 1 && p.nprob <= kMaxProbs, FTD_EINVAL, "gemm: bad problem count");
+    FTD_CHECK(prec != Prec::F64 || out_f64, FTD_EINVAL, "gemm: f64 inputs need f64 output");
+    if (p.M <= 0 || p.N <= 0) return;
+    int ks = split_count(p);
+    if (ks == 0) {
+        FTD_CHECK(p.accumulate, FTD_EINVAL, "gemm: empty contraction without accumulate");
+        return;
+    }
+    const size_t esz = (prec == Prec::F64) ? sizeof(double) : sizeof(float);
+    while (ks > 1 && partial_bytes(p, ks, esz) > partial_cap) --ks;
+    p.ksplit = ks;
+    p.stop = nullptr;
+    p.tstamp = nullptr;
+    const int tm = (p.M + GBM - 1) / GBM, tn = (p.N + GBN - 1) / GBN;
+    dim3 grid(tn, tm, p.nprob * ks);
+    if (prec == Prec::F64)
+        launch<double, double>(ctx, A, B, C, p, grid, static_cast<double*>(partial), nullptr);
+    else if (out_f64)
+        launch<float, double>(ctx, A, B, C, p, grid, static_cast<float*>(partial), nullptr);
+    else
+        launch<float, float>(ctx, A, B, C, p, grid, static_cast<float*>(partial), nullptr);
+    FTD_HIP(hipGetLastError());
+}
+
+void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void* C,
+          GemmParams p, int tag) {
+    FTD_CHECK(p.nprob >= 1 && p.nprob <= kMaxProbs, FTD_EINVAL, "gemm: bad problem count");
+    if (p.M <= 0 || p.N <= 0) return;
+    const int ks = split_count(p);
+    if (ks == 0) {
+        FTD_CHECK(p.accumulate, FTD_EINVAL, "gemm: empty contraction without accumulate");
+        return;
+    }
+    const int tm = (p.M + GBM - 1) / GBM, tn = (p.N + GBN - 1) / GBN;
     p.ksplit = ks;
     p.stop = ctx->kstop;
     size_t esz = (prec == Prec::F64) ? sizeof(double) : sizeof(float);
     void* partial = nullptr;
     if (ks > 1) {
-        size_t need = 2 * (size_t)ks * p.nprob * (size_t)p.M * p.N * esz;
-        ctx->ws_gemm_partial.ensure(ctx, need);
+        ctx->ws_gemm_partial.ensure(ctx, partial_bytes(p, ks, esz));
         partial = ctx->ws_gemm_partial.p;
     }
     dim3 grid(tn, tm, p.nprob * ks);
@@ -310,9 +350,9 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
     }
     FTD_HIP(hipGetLastError());
     if (e0) {
+        double tot_terms = 0;
         e1 = timing_event(ctx);
         FTD_HIP(hipEventRecord(e1, ctx->stream));
-        double tot_terms = 0;
         for (int i = 0; i < p.nprob; ++i) tot_terms += p.prob[i].t1 - p.prob[i].t0;
         const double flops = 8.0 * p.M * (double)p.N * p.K * tot_terms;
         const double cs = 2.0 * (double)esz;
