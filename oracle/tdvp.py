@@ -29,7 +29,12 @@ Readings where the paper is silent (they bind the HIP path too):
     Gram-Schmidt) reorthogonalisation; stop when beta_k |e_k^T exp(zT_k) e_1|
     <= tol |exp(zT_k) e_1|, or when the Krylov space is exhausted;
   * j|Psi_b> is compressed to the same D by the same SVD compression and
-    keeps the norm the truncation leaves.
+    keeps the norm the truncation leaves;
+  * bond expansion (optional, tdvp_step's `expand`): after each site's
+    forward step and gauge factorisation the orthonormal factor is widened,
+    up to D, by the leading directions of H_eff A outside its span, with
+    zero coefficients in the bond matrix, so the state is unchanged and the
+    following backward bond step and site step evolve into them.
 """
 from __future__ import annotations
 
@@ -401,10 +406,49 @@ class Stats:
         self.krylov = []
 
 
-def tdvp_step(psi, Ws, z, tol=1e-14, mmax=40, stats=None):
+# --------------------------------------------------------------------------
+# Bond expansion (adaptive bond dimension; the paper needs larger D at low T
+# and large V but is silent on how a one-site integrator grows it)
+# --------------------------------------------------------------------------
+
+
+def expansion_rank(s, ref, cap, tol):
+    """How many new bond directions to add: the singular values s (descending)
+    of the projected residual that exceed tol * ref, at most cap, never
+    splitting a near-degenerate multiplet (relative gap 1e-8)."""
+    if cap <= 0 or s.size == 0:
+        return 0
+    k = min(int(np.sum(s > tol * ref)), cap)
+    while 0 < k < s.size and (s[k - 1] - s[k]) <= 1e-8 * s[k - 1]:
+        k -= 1
+    return k
+
+
+def expansion_columns(Q, Y, cap, tol):
+    """Orthonormal columns spanning the leading part of Y outside span(Q):
+    Y minus its projection on the orthonormal columns of Q (taken twice),
+    then the left singular vectors whose singular values pass
+    expansion_rank with ref = |Y|_F."""
+    P = Y - Q @ (Q.conj().T @ Y)
+    P = P - Q @ (Q.conj().T @ P)
+    U, s, _ = svd(P)
+    k = expansion_rank(s, np.linalg.norm(Y), cap, tol)
+    return U[:, :k]
+
+
+def tdvp_step(psi, Ws, z, tol=1e-14, mmax=40, stats=None, expand=None):
     """One symmetric sweep pair evolving psi by exp(z H): z = -i dt for real
     time, z = -dtau for imaginary time.  psi must be right-canonical with the
-    centre on site 0; it is returned in the same form."""
+    centre on site 0; it is returned in the same form.
+
+    expand = (D, etol): bond expansion.  After each site's forward step and
+    its gauge factorisation, while the bond it opens is below
+    min(D, what the two neighbouring sites can carry), the orthonormal
+    factor is widened by the leading directions of H_eff A outside its span
+    (expansion_columns with etol); the bond matrix gets zero rows (columns,
+    right to left) for them, so the state is unchanged, and the backward
+    bond step and the next site's step then evolve into the enlarged
+    basis."""
     L = len(psi)
     A = psi.A
     R = right_envs(psi, Ws)
@@ -423,6 +467,14 @@ def tdvp_step(psi, Ws, z, tol=1e-14, mmax=40, stats=None):
         site_evolve(i)
         a, d, _, b = A[i].shape
         Q, C = qr_pos(A[i].reshape(a * d * d, b))
+        if expand is not None:
+            _, dn, _, bn = A[i + 1].shape
+            cap = min(expand[0], a * d * d, dn * dn * bn) - b
+            if cap > 0:
+                Y = heff_apply(Lenv[i], Ws[i], R[i + 1], A[i]).reshape(a * d * d, b)
+                U = expansion_columns(Q, Y, cap, expand[1])
+                Q = np.concatenate([Q, U], axis=1)
+                C = np.concatenate([C, np.zeros((U.shape[1], b), dtype=complex)], axis=0)
         A[i] = Q.reshape(a, d, d, Q.shape[1])
         Lenv[i + 1] = left_env(Lenv[i], A[i], Ws[i], A[i])
         f = lambda x: keff_apply(Lenv[i + 1], R[i + 1], x)
@@ -436,6 +488,14 @@ def tdvp_step(psi, Ws, z, tol=1e-14, mmax=40, stats=None):
     for i in range(L - 1, 0, -1):
         a, d, _, b = A[i].shape
         C, Q = lq_pos(A[i].reshape(a, d * d * b))
+        if expand is not None:
+            ap, dp = A[i - 1].shape[0], A[i - 1].shape[1]
+            cap = min(expand[0], d * d * b, ap * dp * dp) - a
+            if cap > 0:
+                Y = heff_apply(Lenv[i], Ws[i], R[i + 1], A[i]).reshape(a, d * d * b)
+                Wr = expansion_columns(Q.conj().T, Y.conj().T, cap, expand[1]).conj().T
+                Q = np.concatenate([Q, Wr], axis=0)
+                C = np.concatenate([C, np.zeros((a, Wr.shape[0]), dtype=complex)], axis=1)
         A[i] = Q.reshape(Q.shape[0], d, d, b)
         R[i] = right_env(R[i + 1], A[i], Ws[i], A[i])
         f = lambda x: keff_apply(Lenv[i], R[i], x)
@@ -492,10 +552,11 @@ def full_bonds(dims):
 
 
 def thermal_prep(model, Hw, beta, n_imag, n_grow, D, cutoff=1e-10, tol=1e-14,
-                 mmax=40, stats=None):
+                 mmax=40, stats=None, expand_tol=0.0):
     """|Psi_beta> = exp(-beta H/2)|I> in n_imag steps of beta/(2 n_imag):
     the first n_grow steps by propagation and compression (n_grow < 0:
-    adaptive, see growth_done), the rest by one-site TDVP.
+    adaptive, see growth_done), the rest by one-site TDVP, with bond
+    expansion up to D (tdvp_step's expand) when expand_tol > 0.
     Returns the normalised right-canonical state and ln Z."""
     dtau = beta / (2.0 * n_imag)
     psi = identity_mps(model)
@@ -510,8 +571,9 @@ def thermal_prep(model, Hw, beta, n_imag, n_grow, D, cutoff=1e-10, tol=1e-14,
         steps += 1
         if n_grow < 0 and growth_done(before, psi.bond_dims(), D, full):
             break
+    ex = (D, expand_tol) if expand_tol > 0 else None
     for _ in range(n_imag - steps):
-        tdvp_step(psi, Hw, -dtau, tol, mmax, stats)
+        tdvp_step(psi, Hw, -dtau, tol, mmax, stats, expand=ex)
         normalize(psi)
     if stats is not None:
         stats.growth_steps = steps

@@ -346,6 +346,70 @@ def test_norm_and_energy_conserved_in_real_time():
     assert abs(T.overlap(psi, Hw, psi).real - e0) < 1e-10
 
 
+def _low_bond_state(seed=3, D=3):
+    from helpers import random_mps
+    m = small_model(n_mol=3, n_loc=1, n_nl=1, levels=3)
+    dims = Mdl.site_dims(m)
+    return m, dims, OM.hamiltonian_mpo(m), random_mps(dims, D, np.random.default_rng(seed), 0)
+
+
+def test_expansion_at_zero_time_keeps_the_state():
+    """A step of length zero with bond expansion only changes the basis: every
+    exponential is the identity and the new directions enter with zero
+    coefficients, so the represented state is the same to rounding while the
+    bonds grow to min(D, what the neighbouring sites carry); the result is
+    right-canonical (orthonormal rows on every site but the first)."""
+    m, dims, Hw, psi = _low_bond_state()
+    v0 = T.to_dense(psi)
+    before = psi.bond_dims()
+    T.tdvp_step(psi, Hw, 0.0, expand=(12, 1e-10))
+    after = psi.bond_dims()
+    assert all(a >= b for a, b in zip(after, before)) and sum(after) > sum(before)
+    assert max(after) == 12
+    assert np.abs(T.to_dense(psi) - v0).max() < 1e-13 * np.abs(v0).max()
+    for A in psi.A[1:]:
+        a = A.shape[0]
+        M = A.reshape(a, -1)
+        assert np.abs(M @ M.conj().T - np.eye(a)).max() < 1e-12
+
+
+def test_expansion_captures_the_local_residual():
+    """With room for all of it, the widened basis contains the whole part of
+    H_eff A outside the old basis: what is left outside the new span is at
+    rounding level, and the new columns are orthonormal and orthogonal to
+    the old ones."""
+    rng = np.random.default_rng(8)
+    m, n = 60, 5
+    Q, _ = np.linalg.qr(rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n)))
+    Y = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    U = T.expansion_columns(Q, Y, 40, 1e-12)
+    assert U.shape == (m, n)
+    Qn = np.concatenate([Q, U], axis=1)
+    assert np.abs(Qn.conj().T @ Qn - np.eye(2 * n)).max() < 1e-13
+    assert np.linalg.norm(Y - Qn @ (Qn.conj().T @ Y)) < 1e-13 * np.linalg.norm(Y)
+    # a cap keeps the leading part only; nothing is added for Y inside span(Q)
+    assert T.expansion_columns(Q, Y, 2, 1e-12).shape == (m, 2)
+    assert T.expansion_columns(Q, Q @ Y[:n], 40, 1e-10).shape == (m, 0)
+
+
+def test_expansion_conserves_norm_and_energy_in_real_time():
+    """One-site TDVP conserves <psi|psi> and <psi|H|psi> exactly on any
+    manifold (each sub-step is the exponential of a Hermitian operator
+    projected with orthonormal environments); an expansion changes the
+    manifold but not the state, so both stay conserved while the bonds grow.
+    A misplaced zero block, a wrong rectangular bond environment or a
+    non-orthonormal new basis breaks this."""
+    m, dims, Hw, psi = _low_bond_state(seed=5)
+    e0 = T.overlap(psi, Hw, psi).real
+    n0 = T.norm(psi)
+    b0 = sum(psi.bond_dims())
+    for _ in range(6):
+        T.tdvp_step(psi, Hw, -0.15j, expand=(10, 1e-10))
+    assert sum(psi.bond_dims()) > b0
+    assert abs(T.norm(psi) - n0) < 1e-12
+    assert abs(T.overlap(psi, Hw, psi).real - e0) < 1e-10 * max(1.0, abs(e0))
+
+
 def test_g0_correlation_constant_under_tdvp():
     """g = 0: j commutes with H, so C(t) = C(0) = 4/(1 + cosh 2) exactly.  The
     truncated TDVP trajectory drifts only by integrator error, which shrinks
