@@ -247,6 +247,9 @@ def main():
                          "profiler region (HBM counter calibration)")
     ap.add_argument("--verbose", type=int, default=1,
                     help="library progress lines on stderr (0 silent, 2 per compression)")
+    ap.add_argument("--expand-tol", type=float, default=None,
+                    help="bond expansion threshold of the preparation's TDVP steps "
+                         "(default: the workload's; 0 turns expansion off)")
     ap.add_argument("--krylov-tol", type=float, default=None,
                     help="Lanczos stop tolerance (default: the workload's)")
     ap.add_argument("--summarize", nargs=3, metavar=("KIND", "CSV", "LOG"),
@@ -277,8 +280,11 @@ def main():
 
     log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D})")
     t0 = time.perf_counter()
+    if args.expand_tol is not None:
+        r.expand_tol = args.expand_tol
     psi_beta, logz = api.thermal_prep(ctx, H, r.beta, r.n_imag, r.n_grow, r.D, cutoff=r.cutoff,
-                                      precision=args.precision, tol=tol, mmax=mmax)
+                                      precision=args.precision, tol=tol, mmax=mmax,
+                                      expand_tol=r.expand_tol)
     t_prep = time.perf_counter() - t0
     bonds = psi_beta.info()["bond_dims"]
     log(f"[bench] prep {t_prep:.1f} s, ln Z = {logz:.6f}, bonds max {max(bonds)} "

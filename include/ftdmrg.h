@@ -210,14 +210,19 @@ ftd_status ftd_mps_load(ftd_ctx* ctx, const char* path, ftd_mps** out);
  * n_grow steps are propagation-and-compression steps (fourth-order Taylor in
  * Horner form, each stage an exact MPO x MPS product compressed to at most D
  * singular values with s/s_max > cutoff); the remaining steps are one-site
- * TDVP sweeps.  If n_grow < 0 the growth continues until every bond has
- * reached min(D, its maximal rank) or n_imag steps are used.
+ * TDVP sweeps, with the bond expansion of ftd_tdvp_step_expand up to D when
+ * expand_tol > 0, each such step followed by an SVD truncation of the state
+ * at the cutoff (imaginary time damps some added directions to zero weight);
+ * expand_tol = 0: plain one-site sweeps, which keep the bonds the growth
+ * left.  If n_grow < 0 the growth continues until every bond has reached
+ * min(D, its maximal rank) or n_imag steps are used.
  * Output: the normalised state (right-canonical, centre on site 0; caller
  * owns it) and ln Z, Z = <Psi_beta|Psi_beta>.  Errors: FTD_EINVAL (beta < 0,
- * n_imag < 1, D < 1), FTD_ENOCONV, FTD_ENOMEM. */
+ * n_imag < 1, D < 1, expand_tol < 0 or >= 1), FTD_ENOCONV, FTD_ENOMEM. */
 ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t n_imag,
-                            int32_t n_grow, int32_t D, double cutoff, ftd_precision prec,
-                            const ftd_krylov_opts* ko, ftd_mps** psi_beta, double* log_Z);
+                            int32_t n_grow, int32_t D, double cutoff, double expand_tol,
+                            ftd_precision prec, const ftd_krylov_opts* ko, ftd_mps** psi_beta,
+                            double* log_Z);
 
 /* One second-order one-site TDVP projector-splitting step, in place:
  * psi <- exp(z H) psi with z = -i dt_real - dt_imag (real time: dt_imag = 0,
@@ -226,6 +231,21 @@ ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t
  * precision.  Errors: FTD_ENOCONV (Krylov or non-finite), FTD_EINVAL. */
 ftd_status ftd_tdvp_step(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt_real,
                          double dt_imag, const ftd_krylov_opts* ko);
+
+/* One TDVP step as ftd_tdvp_step with bond expansion (the adaptive bond
+ * dimension the paper needs at low temperature and strong coupling): after
+ * each site's forward step and gauge factorisation, while the bond it opens
+ * is below min(D, what the two neighbouring sites can carry), the orthonormal
+ * factor is widened by the leading directions of H_eff A outside its span
+ * (singular values of the projected H_eff A above expand_tol |H_eff A|,
+ * whole near-degenerate multiplets), with zero coefficients in the bond
+ * matrix, so the state is unchanged and the bond's backward step and the
+ * next site's step evolve into the new directions.  Bonds never shrink.
+ * Both sweep directions expand.  Errors: as ftd_tdvp_step; FTD_EINVAL
+ * (D < 1, expand_tol <= 0 or >= 1). */
+ftd_status ftd_tdvp_step_expand(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt_real,
+                                double dt_imag, int32_t D, double expand_tol,
+                                const ftd_krylov_opts* ko);
 
 /* One TDVP step (as ftd_tdvp_step) of each of two different states, run
  * concurrently: psi on the context's stream, phi on a second stream of the

@@ -556,7 +556,9 @@ def thermal_prep(model, Hw, beta, n_imag, n_grow, D, cutoff=1e-10, tol=1e-14,
     """|Psi_beta> = exp(-beta H/2)|I> in n_imag steps of beta/(2 n_imag):
     the first n_grow steps by propagation and compression (n_grow < 0:
     adaptive, see growth_done), the rest by one-site TDVP, with bond
-    expansion up to D (tdvp_step's expand) when expand_tol > 0.
+    expansion up to D (tdvp_step's expand) when expand_tol > 0, each such
+    step followed by an SVD compression at `cutoff` (no bond keeps Schmidt
+    values below cutoff * s_max, which imaginary time can produce).
     Returns the normalised right-canonical state and ln Z."""
     dtau = beta / (2.0 * n_imag)
     psi = identity_mps(model)
@@ -574,6 +576,11 @@ def thermal_prep(model, Hw, beta, n_imag, n_grow, D, cutoff=1e-10, tol=1e-14,
     ex = (D, expand_tol) if expand_tol > 0 else None
     for _ in range(n_imag - steps):
         tdvp_step(psi, Hw, -dtau, tol, mmax, stats, expand=ex)
+        if ex is not None:
+            # imaginary time damps some of the added directions towards zero
+            # weight: drop Schmidt values below the compression cutoff so that
+            # no bond carries a numerically null direction
+            psi = svd_compress(psi, D, cutoff)
         normalize(psi)
     if stats is not None:
         stats.growth_steps = steps

@@ -87,7 +87,9 @@ SIGNATURES = {
     "ftd_mps_set_site": (I32, [P, P, I32, DP, C.c_int64]),
     "ftd_mps_save": (I32, [P, P, C.c_char_p]),
     "ftd_mps_load": (I32, [P, C.c_char_p, PP]),
-    "ftd_thermal_prep": (I32, [P, P, D, I32, I32, I32, D, I32, C.POINTER(KrylovOpts), PP, DP]),
+    "ftd_thermal_prep": (I32, [P, P, D, I32, I32, I32, D, D, I32, C.POINTER(KrylovOpts), PP,
+                               DP]),
+    "ftd_tdvp_step_expand": (I32, [P, P, P, D, D, I32, D, C.POINTER(KrylovOpts)]),
     "ftd_tdvp_pair": (I32, [P, P, P, P, D, D, C.POINTER(KrylovOpts)]),
     "ftd_tdvp_step": (I32, [P, P, P, D, D, C.POINTER(KrylovOpts)]),
     "ftd_apply_compress": (I32, [P, P, P, I32, D, PP]),

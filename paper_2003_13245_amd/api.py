@@ -34,7 +34,8 @@ def _release_all():
     _SHUTDOWN[0] = True
 
 
-__all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_pair",
+__all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_step_expand",
+           "tdvp_pair",
            "corr_current", "mobility", "mobility_sweep", "mobility_grad", "mean_free_path", "fgr_corr", "reduced_density",
            "coherent_length", "qr", "apply_compress", "overlap", "heff_apply", "mps_from_host",
            "mps_load", "gemm", "FtdError"]
@@ -248,19 +249,29 @@ def mpo_build(ctx: Context, model):
 
 
 def thermal_prep(ctx, H, beta, n_imag, n_grow, D, cutoff=1e-10, precision="c128",
-                 tol=1e-14, mmax=40):
+                 tol=1e-14, mmax=40, expand_tol=0.0):
+    """(Psi_beta, ln Z); expand_tol > 0 turns on bond expansion up to D in
+    the one-site TDVP steps."""
     psi = C.c_void_p()
     logz = C.c_double()
     ko = _abi._krylov(tol, mmax)
     check(lib.ftd_thermal_prep(ctx.h, H.h, float(beta), int(n_imag), int(n_grow), int(D),
-                               float(cutoff), PRECISION[precision], C.byref(ko), C.byref(psi),
-                               C.byref(logz)))
+                               float(cutoff), float(expand_tol), PRECISION[precision],
+                               C.byref(ko), C.byref(psi), C.byref(logz)))
     return Mps(ctx, psi), logz.value
 
 
 def tdvp_step(ctx, H, psi, dt_real=0.0, dt_imag=0.0, tol=1e-14, mmax=40):
     ko = _abi._krylov(tol, mmax)
     check(lib.ftd_tdvp_step(ctx.h, H.h, psi.h, float(dt_real), float(dt_imag), C.byref(ko)))
+
+
+def tdvp_step_expand(ctx, H, psi, D, expand_tol, dt_real=0.0, dt_imag=0.0, tol=1e-14,
+                     mmax=40):
+    """One TDVP step with bond expansion up to D (threshold expand_tol)."""
+    ko = _abi._krylov(tol, mmax)
+    check(lib.ftd_tdvp_step_expand(ctx.h, H.h, psi.h, float(dt_real), float(dt_imag), int(D),
+                                   float(expand_tol), C.byref(ko)))
 
 
 def tdvp_pair(ctx, H, psi, phi, dt_real=0.0, dt_imag=0.0, tol=1e-14, mmax=40):

@@ -574,8 +574,9 @@ ftd_status ftd_mps_norm(ftd_ctx* ctx, const ftd_mps* psi, double* out) {
 }
 
 ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t n_imag,
-                            int32_t n_grow, int32_t D, double cutoff, ftd_precision prec,
-                            const ftd_krylov_opts* ko, ftd_mps** psi_beta, double* log_Z) {
+                            int32_t n_grow, int32_t D, double cutoff, double expand_tol,
+                            ftd_precision prec, const ftd_krylov_opts* ko, ftd_mps** psi_beta,
+                            double* log_Z) {
     return guarded([&] {
         FTD_CHECK(ctx && H && psi_beta && log_Z, FTD_EINVAL, "null argument");
         FTD_CHECK(std::isfinite(beta) && beta >= 0.0, FTD_EINVAL, "beta must be >= 0");
@@ -583,6 +584,8 @@ ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t
         FTD_CHECK(D >= 1, FTD_EINVAL, "D must be >= 1");
         FTD_CHECK(std::isfinite(cutoff) && cutoff >= 0.0 && cutoff < 1.0, FTD_EINVAL, "bad cutoff");
         FTD_CHECK(n_grow <= n_imag, FTD_EINVAL, "n_grow > n_imag");
+        FTD_CHECK(std::isfinite(expand_tol) && expand_tol >= 0.0 && expand_tol < 1.0, FTD_EINVAL,
+                  "expand_tol must lie in [0, 1)");
         double tol;
         int mmax;
         check_krylov(ko, tol, mmax);
@@ -629,10 +632,16 @@ ftd_status ftd_thermal_prep(ftd_ctx* ctx, const ftd_mpo* H, double beta, int32_t
                 }
             }
             psi->prec = pr;
+            const int xD = expand_tol > 0.0 ? D : 0;
             for (int s = steps; s < n_imag; ++s) {
-                tdvp_step(c, h, psi, cplx(-dtau, 0.0), tol, mmax);
+                tdvp_step(c, h, psi, cplx(-dtau, 0.0), tol, mmax, xD, expand_tol);
+                // imaginary time damps some added directions towards zero
+                // weight: drop Schmidt values below the cutoff, so no gauge
+                // move meets a numerically null direction
+                if (xD > 0) truncate_canonical(c, psi, D, cutoff);
                 mps_normalize(c, psi);
-                vlog(c, 1, "prep tdvp step %d/%d: %.2f s", s + 1, n_imag, wall_seconds() - t_start);
+                vlog(c, 1, "prep tdvp step %d/%d: max bond %d, %.2f s", s + 1, n_imag, maxb(psi),
+                     wall_seconds() - t_start);
             }
         } catch (...) {
             mps_free(psi);
@@ -653,6 +662,23 @@ ftd_status ftd_tdvp_step(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt
         check_krylov(ko, tol, mmax);
         FTD_CHECK(H->m->L == psi->m->L, FTD_EINVAL, "MPO and MPS lengths differ");
         tdvp_step(&ctx->c, H->m, psi->m, cplx(-dt_imag, -dt_real), tol, mmax);
+    });
+}
+
+ftd_status ftd_tdvp_step_expand(ftd_ctx* ctx, const ftd_mpo* H, ftd_mps* psi, double dt_real,
+                                double dt_imag, int32_t D, double expand_tol,
+                                const ftd_krylov_opts* ko) {
+    return guarded([&] {
+        FTD_CHECK(ctx && H && psi, FTD_EINVAL, "null argument");
+        FTD_CHECK(std::isfinite(dt_real) && std::isfinite(dt_imag), FTD_EINVAL, "non-finite step");
+        FTD_CHECK(D >= 1, FTD_EINVAL, "D must be >= 1");
+        FTD_CHECK(std::isfinite(expand_tol) && expand_tol > 0.0 && expand_tol < 1.0, FTD_EINVAL,
+                  "expand_tol must lie in (0, 1)");
+        double tol;
+        int mmax;
+        check_krylov(ko, tol, mmax);
+        FTD_CHECK(H->m->L == psi->m->L, FTD_EINVAL, "MPO and MPS lengths differ");
+        tdvp_step(&ctx->c, H->m, psi->m, cplx(-dt_imag, -dt_real), tol, mmax, D, expand_tol);
     });
 }
 
@@ -786,7 +812,7 @@ static double run_mobility(ftd_ctx* ctx, const ftd_model& m, double beta, int32_
     double mu = 0.0, mu_cm = 0.0, lz = 0.0;
     try {
         call(ftd_mpo_build(ctx, &m, &H, &J));
-        call(ftd_thermal_prep(ctx, H, beta, n_imag, n_grow, D, cutoff, prec, ko, &psi, &lz));
+        call(ftd_thermal_prep(ctx, H, beta, n_imag, n_grow, D, cutoff, 0.0, prec, ko, &psi, &lz));
         call(ftd_corr_current(ctx, H, J, psi, D, cutoff, dt, n_steps, ko, C.data()));
         call(ftd_mobility(C.data(), n_steps + 1, dt, beta, m.e0, &mu, &mu_cm));
     } catch (...) {

@@ -277,7 +277,7 @@ struct Ctx {
     // scratch
     DBuf ws_gemm_partial, ws_red;
     DBuf ws_T, ws_U, ws_X32, ws_Y32, ws_Krylov, ws_tmp1, ws_tmp2, ws_tmp3, ws_qr;
-    DBuf ws_svd1, ws_svd2, ws_svd3, ws_site, ws_perm;
+    DBuf ws_svd1, ws_svd2, ws_svd3, ws_site, ws_perm, ws_expY, ws_expC;
     // environments of the current sweep: envL[i] left of site i, envR[i]
     // right of site i-1 (i.e. contraction of sites i..L-1)
     std::vector<DBuf> envL, envR;
@@ -338,16 +338,22 @@ void mps_free(Mps* m);
 Mps* mps_clone(const Mps* m);
 Mps* identity_mps(Ctx* ctx, const Mpo* H);
 
-void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax);
+// One second-order one-site TDVP step; expand_D > 0 turns on the bond
+// expansion up to expand_D with threshold expand_tol (relative to |H_eff A|).
+void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax, int expand_D = 0,
+               double expand_tol = 0.0);
 Mps* apply_compress(Ctx* ctx, const Mpo* O, const Mps* psi, int D, double cutoff);
 Mps* compress(Ctx* ctx, Mps* X, int D, double cutoff, bool consume);
+void truncate_canonical(Ctx* ctx, Mps* psi, int D, double cutoff);
 struct TruncOut {
     int k;
     double* Lq;
     double* Rq;
 };
+// abs_floor >= 0 switches to the expansion rule: keep the singular values
+// above abs_floor, at most D, possibly none (k = 0, no buffers returned).
 TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, double cutoff,
-                   bool s_left);
+                   bool s_left, double abs_floor = -1.0);
 Mps* taylor_growth(Ctx* ctx, const Mpo* H, const Mps* psi, double dtau, int D, double cutoff);
 Mps* pc_stage(Ctx* ctx, const Mps* psi, const Mpo* O, const Mps* phi, cplx c, int D, double cutoff);
 Mps* mps_add(Ctx* ctx, const Mps* a, const Mps* b, cplx c);

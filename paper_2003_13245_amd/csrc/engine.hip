@@ -85,7 +85,8 @@ void ctx_release(Ctx& c) {
     (void)hipStreamSynchronize(c.stream);
     for (auto* b : {&c.ws_gemm_partial, &c.ws_red, &c.ws_T, &c.ws_U, &c.ws_X32, &c.ws_Y32,
                     &c.ws_Krylov, &c.ws_tmp1, &c.ws_tmp2, &c.ws_tmp3, &c.ws_qr, &c.ws_svd1,
-                    &c.ws_svd2, &c.ws_svd3, &c.ws_site, &c.ws_perm, &c.ws_A32})
+                    &c.ws_svd2, &c.ws_svd3, &c.ws_site, &c.ws_perm, &c.ws_A32, &c.ws_expY,
+                    &c.ws_expC})
         b->release(&c);
     for (auto& b : c.envL) b.release(&c);
     for (auto& b : c.envR) b.release(&c);
@@ -480,11 +481,13 @@ static void heff(Ctx* ctx, Prec prec, const MpoSite& W, int Da, int Db, const En
     ctx->stats.matvecs++;
 }
 
-// y = K_eff C at the bond between two sites.  L, R: channels of that bond,
-// D x D blocks with L[I] and R[F] materialised as identities.
-static void keff(Ctx* ctx, Prec prec, int w, int idxI, int D, const EnvView& L, const EnvView& R,
-                 const double* x, double* y) {
-    const int64_t n = (int64_t)D * D;
+// y = K_eff C at the bond between two sites.  C is D1 x D2: the left index
+// in the basis of the left environment L (channels of that bond, D1 x D1
+// blocks), the right index in that of R (D2 x D2 blocks); they differ only
+// right after a bond expansion.  L[I] and R[F] are materialised identities.
+static void keff(Ctx* ctx, Prec prec, int w, int idxI, int D1, int D2, const EnvView& L,
+                 const EnvView& R, const double* x, double* y) {
+    const int64_t n = (int64_t)D1 * D2;
     ctx->ws_T.ensure(ctx, esz(prec) * 2 * (size_t)n * w);
     void* T = ctx->ws_T.p;
     const int xs = idxI >= 0 ? idxI : 0;
@@ -492,21 +495,21 @@ static void keff(Ctx* ctx, Prec prec, int w, int idxI, int D, const EnvView& L, 
     std::vector<int> chans;
     for (int c = 0; c < w; ++c)
         if (c != idxI) chans.push_back(c);
-    stage_left(ctx, prec, L, chans, T, xs, D, D, 1, D, n, TAG_KEFF);
+    stage_left(ctx, prec, L, chans, T, xs, D1, D1, 1, D2, n, TAG_KEFF);
     GemmParams p{};
-    p.M = D;
-    p.N = D;
-    p.K = D;
-    p.sAm = D; p.sAk = 1; p.planeA = n; p.a_kcontig = 1;
-    p.sBk = 1; p.sBn = D; p.planeB = n; p.b_kcontig = 1;
-    p.sCm = D; p.sCn = 1; p.planeC = n;
+    p.M = D1;
+    p.N = D2;
+    p.K = D2;
+    p.sAm = D2; p.sAk = 1; p.planeA = n; p.a_kcontig = 1;
+    p.sBk = 1; p.sBn = D2; p.planeB = (int64_t)D2 * D2; p.b_kcontig = 1;
+    p.sCm = D2; p.sCn = 1; p.planeC = n;
     p.nprob = 1;
     p.prob[0].offC = 0;
     p.prob[0].t0 = 0;
     p.prob[0].t1 = w;
     for (int c = 0; c < w; ++c) {
         p.term[c].offA = (int64_t)c * 2 * n;
-        p.term[c].offB = (int64_t)c * 2 * n;
+        p.term[c].offB = (int64_t)c * 2 * D2 * D2;
     }
     gemm(ctx, prec, true, T, R.p, y, p, TAG_KEFF);
     ctx->stats.matvecs++;
@@ -780,45 +783,148 @@ static void build_left_envs(Ctx* ctx, const Mpo* H, const Mps* psi, int upto) {
     }
 }
 
-// new A_{i+1} = C A_{i+1}  (C: Dr x Dr)
-static void absorb_right(Ctx* ctx, Mps* psi, int i, const double* C) {
-    const int D = psi->Dr[i];
+// new A_{i+1} = C A_{i+1}, C: D1 x D2 with D2 the old left bond of A_{i+1};
+// the new left bond is D1 (wider after an expansion of bond i).
+static void absorb_right(Ctx* ctx, Mps* psi, int i, const double* C, int D1) {
+    const int D2 = psi->Dl[i + 1];
     const int64_t nn = psi->size(i + 1);
-    const int64_t cols = nn / D;
-    ctx->ws_site.ensure(ctx, sizeof(double) * 2 * nn);
-    double* tmp = ctx->ws_site.as<double>();
+    const int64_t cols = nn / D2;
+    const int64_t nout = (int64_t)D1 * cols;
+    double* out;
+    if (D1 == D2) {
+        ctx->ws_site.ensure(ctx, sizeof(double) * 2 * nn);
+        out = ctx->ws_site.as<double>();
+    } else {
+        out = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * nout));
+    }
     GemmParams p{};
-    p.M = D; p.N = (int)cols; p.K = D;
-    p.sAm = D; p.sAk = 1; p.planeA = (int64_t)D * D; p.a_kcontig = 1;
+    p.M = D1; p.N = (int)cols; p.K = D2;
+    p.sAm = D2; p.sAk = 1; p.planeA = (int64_t)D1 * D2; p.a_kcontig = 1;
     p.sBk = cols; p.sBn = 1; p.planeB = nn; p.b_kcontig = 0;
-    p.sCm = cols; p.sCn = 1; p.planeC = nn;
+    p.sCm = cols; p.sCn = 1; p.planeC = nout;
     p.nprob = 1; p.prob[0].t1 = 1;
-    gemm(ctx, Prec::F64, true, C, psi->A[i + 1], tmp, p, TAG_NONE);
-    k_copy_f64(ctx, tmp, psi->A[i + 1], 2 * nn);
+    gemm(ctx, Prec::F64, true, C, psi->A[i + 1], out, p, TAG_NONE);
+    if (D1 == D2)
+        k_copy_f64(ctx, out, psi->A[i + 1], 2 * nn);
+    else
+        set_site(ctx, psi, i + 1, D1, psi->Dr[i + 1], out);
 }
-// new A_{i-1} = A_{i-1} C  (C: Dl_i x Dl_i)
-static void absorb_left(Ctx* ctx, Mps* psi, int i, const double* C) {
-    const int D = psi->Dl[i];
+// new A_{i-1} = A_{i-1} C, C: D1 x D2 with D1 the old right bond of A_{i-1};
+// the new right bond is D2 (wider after an expansion of bond i-1).
+static void absorb_left(Ctx* ctx, Mps* psi, int i, const double* C, int D2) {
+    const int D1 = psi->Dr[i - 1];
     const int64_t nn = psi->size(i - 1);
-    const int64_t rows = nn / D;
-    ctx->ws_site.ensure(ctx, sizeof(double) * 2 * nn);
-    double* tmp = ctx->ws_site.as<double>();
+    const int64_t rows = nn / D1;
+    const int64_t nout = rows * D2;
+    double* out;
+    if (D1 == D2) {
+        ctx->ws_site.ensure(ctx, sizeof(double) * 2 * nn);
+        out = ctx->ws_site.as<double>();
+    } else {
+        out = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * nout));
+    }
     GemmParams p{};
-    p.M = (int)rows; p.N = D; p.K = D;
-    p.sAm = D; p.sAk = 1; p.planeA = nn; p.a_kcontig = 1;
-    p.sBk = D; p.sBn = 1; p.planeB = (int64_t)D * D; p.b_kcontig = 0;
-    p.sCm = D; p.sCn = 1; p.planeC = nn;
+    p.M = (int)rows; p.N = D2; p.K = D1;
+    p.sAm = D1; p.sAk = 1; p.planeA = nn; p.a_kcontig = 1;
+    p.sBk = D2; p.sBn = 1; p.planeB = (int64_t)D1 * D2; p.b_kcontig = 0;
+    p.sCm = D2; p.sCn = 1; p.planeC = nout;
     p.nprob = 1; p.prob[0].t1 = 1;
-    gemm(ctx, Prec::F64, true, psi->A[i - 1], C, tmp, p, TAG_NONE);
-    k_copy_f64(ctx, tmp, psi->A[i - 1], 2 * nn);
+    gemm(ctx, Prec::F64, true, psi->A[i - 1], C, out, p, TAG_NONE);
+    if (D1 == D2)
+        k_copy_f64(ctx, out, psi->A[i - 1], 2 * nn);
+    else
+        set_site(ctx, psi, i - 1, psi->Dl[i - 1], D2, out);
+}
+
+// ---------------------------------------------------------- bond expansion
+// Y minus its projection on the orthonormal columns (left) or rows (right)
+// of Q, applied twice; Y is m x r (left) or r x m (right), Q likewise.
+static void project_out(Ctx* ctx, double* Y, const double* Q, int64_t m, int r, bool rows) {
+    const int64_t ny = m * r;
+    ctx->ws_expC.ensure(ctx, sizeof(double) * 2 * (size_t)r * r);
+    double* G = ctx->ws_expC.as<double>();
+    for (int pass = 0; pass < 2; ++pass) {
+        GemmParams p{};
+        p.nprob = 1; p.prob[0].t1 = 1;
+        if (!rows) {   // G = Q^H Y (r x r)
+            p.M = r; p.N = r; p.K = (int)m;
+            p.sAm = 1; p.sAk = r; p.planeA = ny; p.conjA = 1; p.a_kcontig = 0;
+            p.sBk = r; p.sBn = 1; p.planeB = ny; p.b_kcontig = 0;
+            p.sCm = r; p.sCn = 1; p.planeC = (int64_t)r * r;
+            gemm(ctx, Prec::F64, true, Q, Y, G, p, TAG_NONE);
+        } else {       // G = Y Q^H (r x r)
+            p.M = r; p.N = r; p.K = (int)m;
+            p.sAm = m; p.sAk = 1; p.planeA = ny; p.a_kcontig = 1;
+            p.sBk = 1; p.sBn = m; p.planeB = ny; p.conjB = 1; p.b_kcontig = 1;
+            p.sCm = r; p.sCn = 1; p.planeC = (int64_t)r * r;
+            gemm(ctx, Prec::F64, true, Y, Q, G, p, TAG_NONE);
+        }
+        k_scale_cplx(ctx, G, (int64_t)r * r, (int64_t)r * r, -1.0, 0.0);
+        GemmParams q{};
+        q.nprob = 1; q.prob[0].t1 = 1;
+        q.accumulate = 1;
+        if (!rows) {   // Y -= Q G
+            q.M = (int)m; q.N = r; q.K = r;
+            q.sAm = r; q.sAk = 1; q.planeA = ny; q.a_kcontig = 1;
+            q.sBk = r; q.sBn = 1; q.planeB = (int64_t)r * r; q.b_kcontig = 0;
+            q.sCm = r; q.sCn = 1; q.planeC = ny;
+            gemm(ctx, Prec::F64, true, Q, G, Y, q, TAG_NONE);
+        } else {       // Y -= G Q
+            q.M = r; q.N = (int)m; q.K = r;
+            q.sAm = r; q.sAk = 1; q.planeA = (int64_t)r * r; q.a_kcontig = 1;
+            q.sBk = m; q.sBn = 1; q.planeB = ny; q.b_kcontig = 0;
+            q.sCm = m; q.sCn = 1; q.planeC = ny;
+            gemm(ctx, Prec::F64, true, G, Q, Y, q, TAG_NONE);
+        }
+    }
+}
+
+// Bond expansion, first half: Y = H_eff A of the evolved centre A (into
+// ws_expY, float64) and |Y|_F, before the gauge factorisation overwrites A.
+static double expansion_residual(Ctx* ctx, Prec prec, const MpoSite& W, int Da, int Db,
+                                 const EnvView& L, const EnvView& R, const double* A) {
+    const int64_t n = (int64_t)Da * W.d * W.d * Db;
+    ctx->ws_expY.ensure(ctx, sizeof(double) * 2 * (size_t)n);
+    double* Y = ctx->ws_expY.as<double>();
+    heff(ctx, prec, W, Da, Db, L, R, A, Y);
+    ctx->stats.matvecs--;   // not a Krylov matvec
+    k_nrm2(ctx, Y, n, n, ctx->scal + 8);
+    return std::sqrt(read_scalar(ctx, ctx->scal + 8));
+}
+
+// Second half: the leading directions of Y outside the span of the
+// orthonormal factor Q (columns of the m x r factor for a left-to-right step,
+// rows of the r x m factor for right-to-left), at most cap, singular values of
+// the projected Y above tol |Y|_F.  Returns their count and sets *dirs to a
+// new buffer (m x k orthonormal columns, or k x m orthonormal rows), or
+// nullptr when there are none.
+static int expansion_dirs(Ctx* ctx, double ynorm, const double* Q, int64_t m, int r, bool rows,
+                          int cap, double tol, double** dirs) {
+    *dirs = nullptr;
+    if (!(ynorm > 0.0) || !std::isfinite(ynorm)) return 0;
+    double* Y = ctx->ws_expY.as<double>();
+    project_out(ctx, Y, Q, m, r, rows);
+    TruncOut t = rows ? svd_trunc(ctx, Y, r, m, cap, 0.0, true, tol * ynorm)
+                      : svd_trunc(ctx, Y, m, r, cap, 0.0, false, tol * ynorm);
+    if (t.k == 0) return 0;
+    if (rows) {
+        dev_free(ctx, t.Lq);
+        *dirs = t.Rq;
+    } else {
+        dev_free(ctx, t.Rq);
+        *dirs = t.Lq;
+    }
+    return t.k;
 }
 
 // ============================================================ TDVP sweep
-static void tdvp_sweeps(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax);
+static void tdvp_sweeps(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax, int xD,
+                        double xtol);
 
-void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
+void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax, int expand_D,
+               double expand_tol) {
     try {
-        tdvp_sweeps(ctx, H, psi, z, tol, mmax);
+        tdvp_sweeps(ctx, H, psi, z, tol, mmax, expand_D, expand_tol);
     } catch (...) {
         // a failed sweep may leave the sticky breakdown flag set by gauge
         // moves it had already queued: clear it for the next call
@@ -830,7 +936,15 @@ void tdvp_step(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
     }
 }
 
-static void tdvp_sweeps(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax) {
+// The sweep pair of one step.  With xD > 0 every gauge move is followed by
+// a bond expansion while the bond it opens is below min(xD, what the two
+// neighbouring sites can carry): the orthonormal factor gets the leading
+// directions of H_eff A outside its span (threshold xtol |H_eff A|), the bond
+// matrix zero rows (left to right) or columns (right to left) for them, so
+// the state is unchanged; the bond's backward step and the next site's step
+// then run in the enlarged basis.
+static void tdvp_sweeps(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, int mmax, int xD,
+                        double xtol) {
     const int L = psi->L;
     FTD_CHECK(H->L == L, FTD_EINVAL, "MPO and MPS lengths differ");
     const Prec prec = psi->prec;
@@ -848,38 +962,112 @@ static void tdvp_sweeps(Ctx* ctx, const Mpo* H, Mps* psi, cplx z, double tol, in
         auto op = [&](const double* x, double* y) { heff(ctx, prec, W, Da, Db, Lv, Rv, x, y); };
         expm_krylov(ctx, op, psi->A[i], psi->size(i), h, tol, mmax, ctx->khint_site[i]);
     };
-    auto bond_evolve = [&](int i, double* C, int D) {
-        // bond between sites i and i+1: envL[i+1], envR[i+1]
+    // bond between sites i and i+1 (envL[i+1], envR[i+1]); C is D1 x D2
+    auto bond_evolve = [&](int i, double* C, int D1, int D2) {
         const MpoSite& W = H->s[i];
         EnvView Lv = envL_view(ctx, i + 1, prec), Rv = envR_view(ctx, i + 1, prec);
-        auto op = [&](const double* x, double* y) { keff(ctx, prec, W.wr, W.idxI_r, D, Lv, Rv, x, y); };
-        expm_krylov(ctx, op, C, (int64_t)D * D, -h, tol, mmax, ctx->khint_bond[i]);
+        auto op = [&](const double* x, double* y) {
+            keff(ctx, prec, W.wr, W.idxI_r, D1, D2, Lv, Rv, x, y);
+        };
+        expm_krylov(ctx, op, C, (int64_t)D1 * D2, -h, tol, mmax, ctx->khint_bond[i]);
     };
-    for (int i = 0; i < L - 1; ++i) {
-        site_evolve(i);
-        const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
-        ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Db * Db);
-        double* C = ctx->ws_tmp1.as<double>();
-        qr_chol(ctx, psi->A[i], (int64_t)Da * d * d, Db, C, false);
-        EnvView Lv = envL_view(ctx, i, prec);
-        EnvView out = env_get(ctx, ctx->envL, ctx->envL_w, ctx->envL_D, i + 1, H->s[i].wr, Db, prec);
-        env_left_update(ctx, prec, H->s[i], Da, Db, Lv, psi->A[i], out);
-        bond_evolve(i, C, Db);
-        absorb_right(ctx, psi, i, C);
-    }
-    site_evolve(L - 1);
-    site_evolve(L - 1);
-    for (int i = L - 1; i >= 1; --i) {
-        const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
-        ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Da * Da);
-        double* C = ctx->ws_tmp1.as<double>();
-        lq_chol(ctx, psi->A[i], Da, (int64_t)d * d * Db, C, false);
-        EnvView Rv = envR_view(ctx, i + 1, prec);
-        EnvView out = env_get(ctx, ctx->envR, ctx->envR_w, ctx->envR_D, i, H->s[i].wl, Da, prec);
-        env_right_update(ctx, prec, H->s[i], Da, Db, Rv, psi->A[i], out);
-        bond_evolve(i - 1, C, Da);
-        absorb_left(ctx, psi, i, C);
-        site_evolve(i - 1);
+    double* Cx = nullptr;   // the widened bond matrix of an expansion
+    try {
+        for (int i = 0; i < L - 1; ++i) {
+            site_evolve(i);
+            const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
+            const int64_t m = (int64_t)Da * d * d;
+            int cap = 0;
+            double ynorm = 0.0;
+            if (xD > 0) {
+                const int64_t right = (int64_t)psi->d[i + 1] * psi->d[i + 1] * psi->Dr[i + 1];
+                cap = (int)std::min<int64_t>(std::min<int64_t>(xD, m), right) - Db;
+                if (cap > 0)
+                    ynorm = expansion_residual(ctx, prec, H->s[i], Da, Db, envL_view(ctx, i, prec),
+                                               envR_view(ctx, i + 1, prec), psi->A[i]);
+            }
+            ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Db * Db);
+            double* C = ctx->ws_tmp1.as<double>();
+            qr_chol(ctx, psi->A[i], m, Db, C, false);
+            double* dirs = nullptr;
+            const int k = cap > 0 ? expansion_dirs(ctx, ynorm, psi->A[i], m, Db, false, cap, xtol,
+                                                   &dirs)
+                                  : 0;
+            int Dn = Db;
+            if (k > 0) {
+                Dn = Db + k;
+                double* An = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * Dn));
+                k_embed(ctx, psi->A[i], Da, d * d, Db, An, Da, Dn, 0, 0, 1.0, 0.0);
+                k_embed(ctx, dirs, Da, d * d, k, An, Da, Dn, 0, Db, 1.0, 0.0);
+                Cx = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * (size_t)Dn * Db));
+                k_zero(ctx, Cx, sizeof(double) * 2 * (size_t)Dn * Db);
+                k_embed(ctx, C, Db, 1, Db, Cx, Dn, Db, 0, 0, 1.0, 0.0);
+                set_site(ctx, psi, i, Da, Dn, An);
+                dev_free(ctx, dirs);
+                C = Cx;
+            }
+            EnvView Lv = envL_view(ctx, i, prec);
+            EnvView out = env_get(ctx, ctx->envL, ctx->envL_w, ctx->envL_D, i + 1, H->s[i].wr, Dn,
+                                  prec);
+            env_left_update(ctx, prec, H->s[i], Da, Dn, Lv, psi->A[i], out);
+            bond_evolve(i, C, Dn, Db);
+            absorb_right(ctx, psi, i, C, Dn);
+            if (Cx) {
+                FTD_HIP(hipStreamSynchronize(ctx->stream));
+                dev_free(ctx, Cx);
+                Cx = nullptr;
+            }
+        }
+        site_evolve(L - 1);
+        site_evolve(L - 1);
+        for (int i = L - 1; i >= 1; --i) {
+            const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
+            const int64_t m = (int64_t)d * d * Db;
+            int cap = 0;
+            double ynorm = 0.0;
+            if (xD > 0) {
+                const int64_t left = (int64_t)psi->Dl[i - 1] * psi->d[i - 1] * psi->d[i - 1];
+                cap = (int)std::min<int64_t>(std::min<int64_t>(xD, m), left) - Da;
+                if (cap > 0)
+                    ynorm = expansion_residual(ctx, prec, H->s[i], Da, Db, envL_view(ctx, i, prec),
+                                               envR_view(ctx, i + 1, prec), psi->A[i]);
+            }
+            ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Da * Da);
+            double* C = ctx->ws_tmp1.as<double>();
+            lq_chol(ctx, psi->A[i], Da, m, C, false);
+            double* dirs = nullptr;
+            const int k = cap > 0 ? expansion_dirs(ctx, ynorm, psi->A[i], m, Da, true, cap, xtol,
+                                                   &dirs)
+                                  : 0;
+            int Dn = Da;
+            if (k > 0) {
+                Dn = Da + k;
+                double* An = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * Dn));
+                k_embed(ctx, psi->A[i], Da, d * d, Db, An, Dn, Db, 0, 0, 1.0, 0.0);
+                k_embed(ctx, dirs, k, d * d, Db, An, Dn, Db, Da, 0, 1.0, 0.0);
+                Cx = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * (size_t)Da * Dn));
+                k_zero(ctx, Cx, sizeof(double) * 2 * (size_t)Da * Dn);
+                k_embed(ctx, C, Da, 1, Da, Cx, Da, Dn, 0, 0, 1.0, 0.0);
+                set_site(ctx, psi, i, Dn, Db, An);
+                dev_free(ctx, dirs);
+                C = Cx;
+            }
+            EnvView Rv = envR_view(ctx, i + 1, prec);
+            EnvView out = env_get(ctx, ctx->envR, ctx->envR_w, ctx->envR_D, i, H->s[i].wl, Dn, prec);
+            env_right_update(ctx, prec, H->s[i], Dn, Db, Rv, psi->A[i], out);
+            bond_evolve(i - 1, C, Da, Dn);
+            absorb_left(ctx, psi, i, C, Dn);
+            if (Cx) {
+                FTD_HIP(hipStreamSynchronize(ctx->stream));
+                dev_free(ctx, Cx);
+                Cx = nullptr;
+            }
+            site_evolve(i - 1);
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(ctx->stream);
+        dev_free(ctx, Cx);
+        throw;
     }
     // gauge moves were enqueued without waiting: report a breakdown now
     chol_flag_check(ctx);
@@ -967,8 +1155,20 @@ static int truncation_rank(const std::vector<double>& s, int D, double cutoff) {
 // Tall blocks (m >= 2n) are reduced by Householder QR first and one-sided
 // Jacobi runs on the adjoint of the triangular factor; otherwise on T (m >= n)
 // or T^H (m < n).  Returns newly allocated buffers.
+// Expansion rule: the singular values above `floor` (sorted descending), at
+// most cap of them, possibly none, multiplets kept whole.
+static int expansion_rank(const std::vector<double>& s, int cap, double floor) {
+    if (cap <= 0 || s.empty()) return 0;
+    int k = 0;
+    for (double x : s)
+        if (x > floor) ++k;
+    k = std::min(k, cap);
+    while (k > 0 && k < (int)s.size() && (s[k - 1] - s[k]) <= 1e-8 * s[k - 1]) --k;
+    return k;
+}
+
 TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, double cutoff,
-                          bool s_left) {
+                   bool s_left, double abs_floor) {
     const int64_t ns = std::min(m, n);
     const int64_t big = std::max(m, n);
     ctx->ws_svd1.ensure(ctx, sizeof(double) * 2 * (size_t)(big * ns + ns * ns + ns));
@@ -985,7 +1185,7 @@ TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, doubl
         std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return S[x] > S[y]; });
         std::vector<double> ss(ns);
         for (int j = 0; j < ns; ++j) ss[j] = S[perm[j]];
-        k = truncation_rank(ss, D, cutoff);
+        k = abs_floor >= 0.0 ? expansion_rank(ss, D, abs_floor) : truncation_rank(ss, D, cutoff);
     };
     ctx->ws_perm.ensure(ctx, 64 + (sizeof(int) + 3 * sizeof(double)) * (size_t)ns);
     int* dperm = ctx->ws_perm.as<int>();
@@ -1019,6 +1219,12 @@ TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, doubl
             // R = V' S U'^H: left vectors V', right vectors U' = Ub / S
             svd_jacobi(ctx, R, n, n, Ub, Sd, Vb, true);
             finish();
+            if (k == 0) {
+                FTD_HIP(hipStreamSynchronize(ctx->stream));
+                dev_free(ctx, Q);
+                dev_free(ctx, R);
+                return o;
+            }
             upload();
             double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n * k));
             gather(Vb, n, n * n, s_left ? dS : nullptr, 0, G);
@@ -1039,6 +1245,7 @@ TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, doubl
         } else {
             svd_jacobi(ctx, T, m, n, Ub, Sd, Vb);       // T V = U S, Ub = U S (m x n)
             finish();
+            if (k == 0) return o;
             upload();
             double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * k));
             gather(Ub, m, m * n, s_left ? nullptr : dInv, 0, G);
@@ -1055,6 +1262,7 @@ TruncOut svd_trunc(Ctx* ctx, const double* T, int64_t m, int64_t n, int D, doubl
         k_transpose(ctx, T, m, n, m * n, TH, m * n, 1);   // n x m
         svd_jacobi(ctx, TH, n, m, Ub, Sd, Vb);           // T^H = U S V^H, Ub = U S (n x m)
         finish();
+        if (k == 0) return o;
         upload();
         double* G = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * m * k));
         gather(Vb, m, m * m, s_left ? dS : nullptr, 0, G);
@@ -1260,7 +1468,7 @@ static void lq_sweep(Ctx* ctx, Mps* Y) {
         ctx->ws_tmp1.ensure(ctx, sizeof(double) * 2 * (size_t)Da * Da);
         double* Lm = ctx->ws_tmp1.as<double>();
         lq_chol(ctx, Y->A[i], Da, (int64_t)d * d * Db, Lm);
-        absorb_left(ctx, Y, i, Lm);
+        absorb_left(ctx, Y, i, Lm, Y->Dl[i]);
     }
 }
 
@@ -1405,6 +1613,35 @@ static Mps* compress_terms(Ctx* ctx, const std::vector<ZipTerm>& terms, int D, d
     vlog(ctx, 2, "compress %d terms, widest bond %d: metric %.3f s, truncation %.3f s "
          "(svd %.3f s), lq sweep %.3f s", nt, wmax, t1 - t0, t2 - t1, t_svd, wall_seconds() - t2);
     return Y;
+}
+
+// SVD truncation of a right-canonical state in place: left to right, each
+// centre A_i (Dl d^2 x Dr) keeps at most D singular values with
+// s/s_max > cutoff (whole multiplets), its left vectors become the site and
+// S V^H moves into the next site; then an LQ sweep restores right-canonical
+// form.  For a right-canonical input this is the SVD compression of the
+// state (the right-canonical sweep compress() starts with is the identity).
+void truncate_canonical(Ctx* ctx, Mps* psi, int D, double cutoff) {
+    const int L = psi->L;
+    for (int i = 0; i < L - 1; ++i) {
+        const int Da = psi->Dl[i], Db = psi->Dr[i], d = psi->d[i];
+        const int64_t m = (int64_t)Da * d * d;
+        TruncOut t = svd_trunc(ctx, psi->A[i], m, Db, D, cutoff, false);
+        try {
+            set_site(ctx, psi, i, Da, t.k, t.Lq);
+            t.Lq = nullptr;
+            absorb_right(ctx, psi, i, t.Rq, t.k);
+        } catch (...) {
+            FTD_HIP(hipStreamSynchronize(ctx->stream));
+            dev_free(ctx, t.Lq);
+            dev_free(ctx, t.Rq);
+            throw;
+        }
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+        dev_free(ctx, t.Rq);
+    }
+    lq_sweep(ctx, psi);
+    FTD_HIP(hipStreamSynchronize(ctx->stream));
 }
 
 Mps* compress(Ctx* ctx, Mps* X, int D, double cutoff, bool consume) {

@@ -109,6 +109,7 @@ class Run:
     krylov_tol: float = 1e-14
     krylov_mmax: int = 40
     cutoff: float = 1e-10  # relative singular-value cutoff for compression
+    expand_tol: float = 0.0  # bond expansion threshold of the one-site TDVP steps (0: off)
 
 
 @dataclasses.dataclass
@@ -182,7 +183,8 @@ def rubrene_shaped(n_mol=21, n_loc=4, n_nl=1, levels=10, D=128, T=300.0,
     dt = fs(dt_fs)
     n_steps = int(round(t_fs / dt_fs))
     r = Run(beta=beta, n_imag=n_imag, n_grow=1, D=D, dt=dt, n_steps=n_steps,
-            krylov_tol=1e-14 if precision == "c128" else 1e-8)
+            krylov_tol=1e-14 if precision == "c128" else 1e-8,
+            expand_tol=1e-8 if precision == "c128" else 1e-5)
     name = f"hp_n{n_mol}_loc{n_loc}_nl{n_nl}_d{levels}_D{D}_T{T:g}"
     return Workload(name, m, r, precision)
 
