@@ -3,12 +3,16 @@
 // One workgroup (4 wavefronts) computes a 64x64 tile of C.  The k loop is
 // software-pipelined: the next 16-deep tile is loaded into registers while
 // the current one (in one of two LDS buffers) feeds the MFMAs.  Each wavefront
-// owns a 32x32 quadrant as 2x2 blocks of 16x16 MFMA outputs; every k-step of
-// 4 issues four real products per block (re*re, im*im, re*im, im*re) into
-// three accumulators, so Re C = RR - II and Im C = RI + IR.  Operands are
-// staged through LDS as [plane][k][m] / [plane][k][n] so that the 16 lanes
-// sharing a k row read 16 consecutive elements.  Conjugation is applied while
-// staging.  Problems (independent outputs) and summed terms (products added
+// owns a 32x32 quadrant as 2x2 blocks of 16x16 MFMA outputs.  Complex
+// products: float64 issues four real products per block and k-step (re*re,
+// im*im, re*im, im*re) into three accumulators, Re C = RR - II and
+// Im C = RI + IR; float32 uses the three-multiplication form (Gauss):
+// P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), Re C = P1 - P2,
+// Im C = P3 - P1 - P2, with the sums formed when staging (a third LDS plane
+// per operand), which takes a quarter of the matrix-core work away at a
+// rounding cost of order eps |A| |B|.  Operands are staged through LDS as
+// [plane][k][m] / [plane][k][n] so that the 16 lanes sharing a k row read 16
+// consecutive elements.  Conjugation is applied while staging.  Problems (independent outputs) and summed terms (products added
 // into the same output) are described by offset tables passed by value, which
 // is how the channel sums of the effective Hamiltonian map onto one launch.
 #include "common.h"
@@ -50,11 +54,15 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
                                                    Tout* __restrict__ C,
                                                    Tin* __restrict__ partial, const GemmParams p) {
     typedef typename AccT<Tin>::type acc_t;
+    // three-multiplication complex product in float32 (see the file comment)
+    constexpr bool G3 = sizeof(Tin) == 4;
+    constexpr int NPL = G3 ? 3 : 2;
     if (p.stop && *p.stop) return;
     if (p.tstamp && threadIdx.x == 0) atomicMin(p.tstamp, (unsigned long long)wall_clock64());
-    // two LDS buffers (double buffering), each [plane][k][m] / [plane][k][n]
-    __shared__ Tin As[2][2][GBK][GBM + GPAD];
-    __shared__ Tin Bs[2][2][GBK][GBN + GPAD];
+    // two LDS buffers (double buffering), each [plane][k][m] / [plane][k][n];
+    // plane 2 (float32 only) holds re + im
+    __shared__ Tin As[2][NPL][GBK][GBM + GPAD];
+    __shared__ Tin Bs[2][NPL][GBK][GBN + GPAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -122,16 +130,20 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
             const int mm = AK ? (tid >> 4) + 16 * i : (tid & 63);
             const int kk = AK ? (tid & 15) : (tid >> 6) + 4 * i;
             const bool in = (inA >> i) & 1u;
-            As[buf][0][kk][mm] = in ? ra[i] : Tin(0);
-            As[buf][1][kk][mm] = in ? sa * ia[i] : Tin(0);
+            const Tin xr = in ? ra[i] : Tin(0), xi = in ? sa * ia[i] : Tin(0);
+            As[buf][0][kk][mm] = xr;
+            As[buf][1][kk][mm] = xi;
+            if constexpr (G3) As[buf][NPL - 1][kk][mm] = xr + xi;
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int nn = BKC ? (tid >> 4) + 16 * i : (tid & 63);
             const int kk = BKC ? (tid & 15) : (tid >> 6) + 4 * i;
             const bool in = (inB >> i) & 1u;
-            Bs[buf][0][kk][nn] = in ? rb[i] : Tin(0);
-            Bs[buf][1][kk][nn] = in ? sb * ib[i] : Tin(0);
+            const Tin xr = in ? rb[i] : Tin(0), xi = in ? sb * ib[i] : Tin(0);
+            Bs[buf][0][kk][nn] = xr;
+            Bs[buf][1][kk][nn] = xi;
+            if constexpr (G3) Bs[buf][NPL - 1][kk][nn] = xr + xi;
         }
     };
 
@@ -159,15 +171,32 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
                 br[j] = Bs[cur][0][kr][wn * 32 + j * 16 + c];
                 bi[j] = Bs[cur][1][kr][wn * 32 + j * 16 + c];
             }
+            if constexpr (G3) {
+                // RR = Ar Br, II = Ai Bi, IM = (Ar + Ai)(Br + Bi)
+                Tin as[2], bs[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i) as[i] = As[cur][NPL - 1][kr][wm * 32 + i * 16 + c];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    RR[i][j] = mfma4(ar[i], br[j], RR[i][j]);
-                    II[i][j] = mfma4(ai[i], bi[j], II[i][j]);
-                    IM[i][j] = mfma4(ar[i], bi[j], IM[i][j]);
-                    IM[i][j] = mfma4(ai[i], br[j], IM[i][j]);
-                }
+                for (int j = 0; j < 2; ++j) bs[j] = Bs[cur][NPL - 1][kr][wn * 32 + j * 16 + c];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        RR[i][j] = mfma4(ar[i], br[j], RR[i][j]);
+                        II[i][j] = mfma4(ai[i], bi[j], II[i][j]);
+                        IM[i][j] = mfma4(as[i], bs[j], IM[i][j]);
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        RR[i][j] = mfma4(ar[i], br[j], RR[i][j]);
+                        II[i][j] = mfma4(ai[i], bi[j], II[i][j]);
+                        IM[i][j] = mfma4(ar[i], bi[j], IM[i][j]);
+                        IM[i][j] = mfma4(ai[i], br[j], IM[i][j]);
+                    }
+            }
         }
         // the other buffer was last read in the previous iteration, which
         // ended with a barrier
@@ -187,7 +216,7 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
                 const int col = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (row < p.M && col < p.N) {
                     const Tin cr = RR[i][j][r] - II[i][j][r];
-                    const Tin ci = IM[i][j][r];
+                    const Tin ci = G3 ? IM[i][j][r] - RR[i][j][r] - II[i][j][r] : IM[i][j][r];
                     if (p.ksplit > 1) {
                         const int64_t idx = ((int64_t)split * p.nprob + prob) * MN + (int64_t)row * p.N + col;
                         partial[idx] = cr;
