@@ -43,10 +43,11 @@ typedef enum {
     FTD_C128 = 0,        /* every contraction in complex float64               */
     FTD_C64 = 1,         /* contractions in complex float32 on MFMA, Krylov,
                             QR, norms and log Z in float64                     */
-    FTD_BF16X3 = 2       /* reserved for contractions as three bf16 split
-                            products with float32 accumulation: not built,
-                            every call that takes a precision rejects it with
-                            FTD_EINVAL                                         */
+    FTD_BF16X3 = 2       /* contractions on bf16 matrix cores: every float32
+                            operand split as hi + lo (two bf16), each real
+                            product as hi*hi + hi*lo + lo*hi, float32
+                            accumulation (relative error ~2^-17 per product);
+                            Krylov, QR, norms and log Z in float64          */
 } ftd_precision;
 
 typedef struct ftd_ctx ftd_ctx;
@@ -417,7 +418,8 @@ ftd_status ftd_svd_trunc(ftd_ctx* ctx, int32_t M, int32_t N, const double* T, in
  * transpose or conjugate transpose per operand (trans = 0, 1, 2), M x N
  * result, inner dimension K; host buffers interleaved complex, row-major:
  * A is M x K (trans 0) or K x M (trans 1, 2), B is K x N (0) or N x K (1, 2).
- * precision FTD_C128 (float64) or FTD_C64 (float32 operands, float64 out).
+ * precision FTD_C128 (float64), FTD_C64 (float32 operands, float64 out) or
+ * FTD_BF16X3 (float32 operands, bf16 split products, float64 out).
  * Used by the kernel parity tests. */
 ftd_status ftd_gemm(ftd_ctx* ctx, int32_t precision, int32_t M, int32_t N, int32_t K,
                     int32_t transA, int32_t transB, const double* A, const double* B, double* C);

@@ -40,8 +40,7 @@ static void check_krylov(const ftd_krylov_opts* ko, double& tol, int& mmax) {
 }
 
 static Prec to_prec(int32_t p) {
-    FTD_CHECK(p != FTD_BF16X3, FTD_EINVAL, "bf16x3 contractions are not built");
-    FTD_CHECK(p == FTD_C128 || p == FTD_C64, FTD_EINVAL, "unknown precision");
+    FTD_CHECK(p == FTD_C128 || p == FTD_C64 || p == FTD_BF16X3, FTD_EINVAL, "unknown precision");
     return static_cast<Prec>(p);
 }
 
@@ -486,7 +485,8 @@ ftd_status ftd_mps_load(ftd_ctx* ctx, const char* path, ftd_mps** out) {
             get(&prec, 4);
             get(&log_norm, 8);
             FTD_CHECK(L >= 1 && L <= (1 << 20), FTD_EINVAL, "bad site count in state file");
-            FTD_CHECK(prec == FTD_C128 || prec == FTD_C64, FTD_EINVAL, "bad precision in state file");
+            FTD_CHECK(prec == FTD_C128 || prec == FTD_C64 || prec == FTD_BF16X3, FTD_EINVAL,
+                      "bad precision in state file");
             FTD_CHECK(std::isfinite(log_norm), FTD_EINVAL, "non-finite log norm in state file");
             std::vector<int> Dl(L), d(L), Dr(L);
             for (int i = 0; i < L; ++i) {
@@ -1083,7 +1083,6 @@ ftd_status ftd_gemm(ftd_ctx* ctx, int32_t precision, int32_t M, int32_t N, int32
         FTD_CHECK(M >= 1 && N >= 1 && K >= 1, FTD_EINVAL, "empty GEMM");
         FTD_CHECK(transA >= 0 && transA <= 2 && transB >= 0 && transB <= 2, FTD_EINVAL, "bad trans");
         const Prec pr = to_prec(precision);
-        FTD_CHECK(pr != Prec::BF16X3, FTD_EINVAL, "ftd_gemm: c128 or c64 only");
         Ctx* c = &ctx->c;
         const int64_t na = (int64_t)M * K, nb = (int64_t)K * N, nc = (int64_t)M * N;
         const size_t es = pr == Prec::F64 ? 8 : 4;

@@ -239,6 +239,211 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(const Tin* __restrict__ A,
     }
 }
 
+// ------------------------------------------------------------ BF16x3 path
+// Complex GEMM on float32 data with bf16 matrix cores: every float32
+// operand x is split when staging into x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi) (round to nearest even), and each real product a b
+// is formed as a_hi b_hi + a_hi b_lo + a_lo b_hi with float32 accumulation
+// (the dropped a_lo b_lo and the split leave a relative error of order
+// 2^-17 per product).  v_mfma_f32_16x16x32_bf16: lane l holds rows/columns
+// l % 16 and the eight k values 8 (l / 16) .. 8 (l / 16) + 7 of its operand;
+// the 16x16 float32 result uses the float32 16x16x4 layout.  One workgroup
+// (4 wavefronts, each a 32x32 quadrant as 2x2 blocks) per 64x64 tile; k
+// advances 32 at a time.  The operands sit in LDS as [plane][row][k] with k
+// contiguous (planes re_hi, re_lo, im_hi, im_lo), so each lane fetches its
+// eight values with one 16-byte read; the next k-tile's global loads are in
+// flight during the current tile's MFMAs (one LDS buffer, register staging).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits_rn(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite x)
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_float(unsigned short h) {
+    return __uint_as_float((unsigned)h << 16);
+}
+
+constexpr int XBK = 32, XPAD = 8;
+
+template <typename Tout, bool AK, bool BKC>
+__global__ __launch_bounds__(GNT) void gemm_bx3_kernel(const float* __restrict__ A,
+                                                       const float* __restrict__ B,
+                                                       Tout* __restrict__ C,
+                                                       float* __restrict__ partial,
+                                                       const GemmParams p) {
+    if (p.stop && *p.stop) return;
+    if (p.tstamp && threadIdx.x == 0) atomicMin(p.tstamp, (unsigned long long)wall_clock64());
+    // [plane: re_hi, re_lo, im_hi, im_lo][row][k]
+    __shared__ __align__(16) unsigned short As[4][GBM][XBK + XPAD];
+    __shared__ __align__(16) unsigned short Bs[4][GBN][XBK + XPAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int prob = blockIdx.z % p.nprob;
+    const int split = blockIdx.z / p.nprob;
+
+    f4 RR[2][2], II[2][2], IM[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            RR[i][j] = f4{0, 0, 0, 0};
+            II[i][j] = f4{0, 0, 0, 0};
+            IM[i][j] = f4{0, 0, 0, 0};
+        }
+
+    const int ktiles = (p.K + XBK - 1) / XBK;
+    const int t0 = p.prob[prob].t0, t1 = p.prob[prob].t1;
+    const int total = (t1 - t0) * ktiles;
+    const int per = (total + p.ksplit - 1) / p.ksplit;
+    const int g0 = split * per;
+    const int g1 = min(total, g0 + per);
+    const float sa = p.conjA ? -1.f : 1.f;
+    const float sb = p.conjB ? -1.f : 1.f;
+
+    // a 64 x 32 tile of A and a 32 x 64 tile of B: 8 (re, im) pairs each per
+    // thread; element e = tid + 256 i, k fastest when the operand is
+    // k-contiguous, else the row index fastest.  Clamped addresses keep every
+    // load valid; out-of-range elements are zeroed at staging.
+    float ra[8], ia[8], rb[8], ib[8];
+    unsigned inA = 0, inB = 0;
+    auto a_rc = [&](int e, int& r, int& k) {
+        if (AK) { r = e / XBK; k = e % XBK; } else { r = e % GBM; k = e / GBM; }
+    };
+    auto b_rc = [&](int e, int& r, int& k) {
+        if (BKC) { r = e / XBK; k = e % XBK; } else { r = e % GBN; k = e / GBN; }
+    };
+    auto fetch = [&](int g) {
+        const int t = t0 + g / ktiles;
+        const int k0 = (g % ktiles) * XBK;
+        const float* Ab = A + p.term[t].offA;
+        const float* Bb = B + p.term[t].offB;
+        inA = 0;
+        inB = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            int mm, kk;
+            a_rc(tid + 256 * i, mm, kk);
+            const int gm = m0 + mm, gk = k0 + kk;
+            inA |= (unsigned)(gm < p.M && gk < p.K) << i;
+            const int64_t idx = (int64_t)min(gm, p.M - 1) * p.sAm + (int64_t)min(gk, p.K - 1) * p.sAk;
+            ra[i] = Ab[idx];
+            ia[i] = Ab[idx + p.planeA];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            int nn, kk;
+            b_rc(tid + 256 * i, nn, kk);
+            const int gn = n0 + nn, gk = k0 + kk;
+            inB |= (unsigned)(gn < p.N && gk < p.K) << i;
+            const int64_t idx = (int64_t)min(gk, p.K - 1) * p.sBk + (int64_t)min(gn, p.N - 1) * p.sBn;
+            rb[i] = Bb[idx];
+            ib[i] = Bb[idx + p.planeB];
+        }
+    };
+    auto split_store = [](unsigned short (*P)[XBK + XPAD], unsigned short (*Q)[XBK + XPAD], int r,
+                          int k, float x) {
+        const unsigned short h = bf16_bits_rn(x);
+        P[r][k] = h;
+        Q[r][k] = bf16_bits_rn(x - bf16_bits_to_float(h));
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            int mm, kk;
+            a_rc(tid + 256 * i, mm, kk);
+            const bool in = (inA >> i) & 1u;
+            split_store(As[0], As[1], mm, kk, in ? ra[i] : 0.f);
+            split_store(As[2], As[3], mm, kk, in ? sa * ia[i] : 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            int nn, kk;
+            b_rc(tid + 256 * i, nn, kk);
+            const bool in = (inB >> i) & 1u;
+            split_store(Bs[0], Bs[1], nn, kk, in ? rb[i] : 0.f);
+            split_store(Bs[2], Bs[3], nn, kk, in ? sb * ib[i] : 0.f);
+        }
+    };
+    auto frag = [](const unsigned short* row, int kq) {
+        return *reinterpret_cast<const bf16x8*>(row + 8 * kq);
+    };
+
+    if (g0 < g1) fetch(g0);
+    for (int g = g0; g < g1; ++g) {
+        // the previous tile's MFMAs are done reading LDS
+        __syncthreads();
+        stash();
+        __syncthreads();
+        if (g + 1 < g1) fetch(g + 1);
+        const int c = lane & 15, kq = lane >> 4;
+        bf16x8 a[2][4], b[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[i][q] = frag(As[q][wm * 32 + i * 16 + c], kq);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[j][q] = frag(Bs[q][wn * 32 + j * 16 + c], kq);
+        // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                RR[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], RR[i][j], 0, 0, 0);
+                RR[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], RR[i][j], 0, 0, 0);
+                RR[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], RR[i][j], 0, 0, 0);
+                II[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][3], b[j][2], II[i][j], 0, 0, 0);
+                II[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][3], II[i][j], 0, 0, 0);
+                II[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][2], II[i][j], 0, 0, 0);
+                IM[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][2], IM[i][j], 0, 0, 0);
+                IM[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][3], IM[i][j], 0, 0, 0);
+                IM[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][3], b[j][0], IM[i][j], 0, 0, 0);
+                IM[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][1], IM[i][j], 0, 0, 0);
+                IM[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][2], IM[i][j], 0, 0, 0);
+                IM[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][0], IM[i][j], 0, 0, 0);
+            }
+    }
+
+    const int64_t MN = (int64_t)p.M * p.N;
+    const int64_t pplane = (int64_t)p.ksplit * p.nprob * MN;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + i * 16 + AccT<float>::row(lane, r);
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < p.M && col < p.N) {
+                    const float cr = RR[i][j][r] - II[i][j][r];
+                    const float ci = IM[i][j][r];
+                    if (p.ksplit > 1) {
+                        const int64_t idx = ((int64_t)split * p.nprob + prob) * MN + (int64_t)row * p.N + col;
+                        partial[idx] = cr;
+                        partial[idx + pplane] = ci;
+                    } else {
+                        const int64_t idx = p.prob[prob].offC + (int64_t)row * p.sCm + (int64_t)col * p.sCn;
+                        if (p.accumulate) {
+                            C[idx] += (Tout)cr;
+                            C[idx + p.planeC] += (Tout)ci;
+                        } else {
+                            C[idx] = (Tout)cr;
+                            C[idx + p.planeC] = (Tout)ci;
+                        }
+                    }
+                }
+            }
+    if (p.tstamp) {
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(p.tstamp + 1, (unsigned long long)wall_clock64());
+    }
+}
+
 template <typename Tin, typename Tout>
 __global__ void gemm_reduce_kernel(const Tin* __restrict__ partial, Tout* __restrict__ C,
                                    const GemmParams p) {
@@ -265,6 +470,28 @@ __global__ void gemm_reduce_kernel(const Tin* __restrict__ partial, Tout* __rest
             C[idx] = sr;
             C[idx + p.planeC] = si;
         }
+    }
+}
+
+template <typename Tout>
+static void launch_bx3(Ctx* ctx, const void* A, const void* B, void* C, const GemmParams& p,
+                       dim3 grid, float* partial, hipEvent_t mid) {
+    const float* a = static_cast<const float*>(A);
+    const float* b = static_cast<const float*>(B);
+    Tout* c = static_cast<Tout*>(C);
+    if (p.a_kcontig && p.b_kcontig)
+        gemm_bx3_kernel<Tout, true, true><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    else if (p.a_kcontig && !p.b_kcontig)
+        gemm_bx3_kernel<Tout, true, false><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    else if (!p.a_kcontig && p.b_kcontig)
+        gemm_bx3_kernel<Tout, false, true><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    else
+        gemm_bx3_kernel<Tout, false, false><<<grid, GNT, 0, ctx->stream>>>(a, b, c, partial, p);
+    if (mid) FTD_HIP(hipEventRecord(mid, ctx->stream));
+    if (p.ksplit > 1) {
+        const int64_t tot = (int64_t)p.M * p.N * p.nprob;
+        int nb = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+        gemm_reduce_kernel<float, Tout><<<nb, 256, 0, ctx->stream>>>(partial, c, p);
     }
 }
 
@@ -334,6 +561,10 @@ void gemm_in(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, vo
     dim3 grid(tn, tm, p.nprob * ks);
     if (prec == Prec::F64)
         launch<double, double>(ctx, A, B, C, p, grid, static_cast<double*>(partial), nullptr);
+    else if (prec == Prec::BF16X3 && out_f64)
+        launch_bx3<double>(ctx, A, B, C, p, grid, static_cast<float*>(partial), nullptr);
+    else if (prec == Prec::BF16X3)
+        launch_bx3<float>(ctx, A, B, C, p, grid, static_cast<float*>(partial), nullptr);
     else if (out_f64)
         launch<float, double>(ctx, A, B, C, p, grid, static_cast<float*>(partial), nullptr);
     else
@@ -372,6 +603,10 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
     if (prec == Prec::F64) {
         FTD_CHECK(out_f64, FTD_EINVAL, "gemm: f64 inputs need f64 output");
         launch<double, double>(ctx, A, B, C, p, grid, static_cast<double*>(partial), em);
+    } else if (prec == Prec::BF16X3 && out_f64) {
+        launch_bx3<double>(ctx, A, B, C, p, grid, static_cast<float*>(partial), em);
+    } else if (prec == Prec::BF16X3) {
+        launch_bx3<float>(ctx, A, B, C, p, grid, static_cast<float*>(partial), em);
     } else if (out_f64) {
         launch<float, double>(ctx, A, B, C, p, grid, static_cast<float*>(partial), em);
     } else {
