@@ -7,12 +7,15 @@ bond dimension 128, T = 300 K), synthetic seeded parameters.
 
 A step is one step of the C(t) loop: one second-order one-site TDVP step of
 Psi_beta and one of j Psi_beta (run concurrently on two streams), and the
-overlap <Psi|j|Phi>.  The inputs
-(Psi_beta from the imaginary-time preparation and j Psi_beta compressed to
-D) are prepared before the timed region and stay resident in HBM.  The
-headline value is the mixed-precision path (complex64 contractions on MFMA,
-float64 Krylov/QR/norms); the same steps are then repeated in float64 from
-the same inputs, which gives the speedup and the C(t) error of the mixed path.
+overlap <Psi|j|Phi>.  The inputs (Psi_beta from the imaginary-time
+preparation, whose one-site steps expand the bonds up to D, and j Psi_beta
+compressed to D) are prepared before the timed region and stay resident in
+HBM.  The headline value is the mixed-precision path (complex64 contractions
+on MFMA, float64 Krylov/QR/norms).  From the same inputs the first
+--compare-steps steps are then run in float64 (Krylov tolerance 1e-14), the
+reference for the C(t) and window-mobility errors, and with the BF16x3
+split-product contractions.  The oracle's time for a pair-step is assembled
+from its kernels timed at every site shape of the two states (cpu_baseline).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build targets one GPU.
 """
@@ -31,7 +34,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 METRIC = "TDVP steps/s + H_eff TFLOP/s, mixed vs FP64 at C(t) rel err 1e-4, D=128"
-PEAK = {"c64": 157.3, "c128": 78.6}   # TFLOP/s, dense MFMA (FP32, FP64)
+# TFLOP/s, dense MFMA peaks of MI355X (FP32, FP64, BF16)
+PEAK = {"c64": 157.3, "c128": 78.6, "bf16": 2516.6}
 
 
 def log(*a):
@@ -149,10 +153,13 @@ def summarize_rows(kind, label, window, rows):
 
 def kernel_name(kind):
     """Name of the GEMM kernel instance with identity `kind` (see ftd_stats)."""
-    tin = "double" if (kind >> 3) == 0 else "float"
+    prec = kind >> 3
+    tin = "double" if prec == 0 else "float"
     tout = "double" if (kind & 4) else tin
     ak = "true" if (kind & 2) else "false"
     bk = "true" if (kind & 1) else "false"
+    if prec == 2:
+        return f"ftd::gemm_bx3_kernel<{tout}, {ak}, {bk}>"
     return f"ftd::gemm_kernel<{tin}, {tout}, {ak}, {bk}>"
 
 
@@ -193,41 +200,100 @@ def run_steps(api, ctx, H, J, psi0, phi0, steps, dt, tol, mmax, timing, roctx=No
     return np.array(C), t1 - t0, st
 
 
-def cpu_baseline(wl, matvecs_per_step, budget_s=20.0):
-    """Oracle H_eff matvecs at the workload's widest phonon-site shape (random
-    environments of the oracle MPO's channel count), scaled to a step by the
-    number of matvecs one step issued on the GPU."""
-    from oracle import mpo as OM
-    from oracle import tdvp as T
-    m = wl.model
-    Hw = OM.hamiltonian_mpo(m)
-    D = wl.run.D
-    L = len(Hw)
-    site = next(i for i in range(L // 2, L) if Hw[i].shape[2] > 2)
-    W = Hw[site]
-    d = W.shape[2]
-    rng = np.random.default_rng(0)
-    Lenv = rng.standard_normal((W.shape[0], D, D)) + 1j * rng.standard_normal((W.shape[0], D, D))
-    Renv = rng.standard_normal((W.shape[1], D, D)) + 1j * rng.standard_normal((W.shape[1], D, D))
-    A = rng.standard_normal((D, d, d, D)) + 1j * rng.standard_normal((D, d, d, D))
+def blas_info():
+    """(threads, vendor) of the BLAS numpy uses on this host."""
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        pools = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if pools:
+            return int(max(p.get("num_threads", 1) for p in pools)), pools[0].get("internal_api", "?")
     except Exception:
-        cores = os.cpu_count() or 1
-    n, t0 = 0, time.perf_counter()
-    while True:
-        T.heff_apply(Lenv, W, Renv, A)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or n >= 50:
-            break
-    per = el / n
-    step_s = per * matvecs_per_step
-    return {"value": 1.0 / step_s, "unit": "pair-steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} oracle H_eff matvecs at the D={D}, d={d} phonon-site shape "
-                      f"({per:.3f} s each, {el:.1f} s total), scaled by the "
-                      f"{matvecs_per_step:.0f} matvecs of one GPU step"}
+        pass
+    return os.cpu_count() or 1, "?"
+
+
+def cpu_baseline(wl, states, krylov_mean, rep_s=0.25):
+    """The oracle's time for one pair-step of this workload, assembled from
+    the oracle's own kernels timed on this host at every distinct site shape
+    of the two states as they enter the timed steps.  One state-step visits
+    every site twice (left-to-right, right-to-left sweep); a visit is
+    krylov_mean H_eff matvecs (the GPU run's mean Krylov vectors per
+    exponential), one gauge QR, one environment update and krylov_mean K_eff
+    matvecs on the bond; a pair-step is both states plus one overlap (one
+    transfer step per site).  Each distinct shape is timed once per kernel
+    (repeated up to rep_s), not extrapolated from one shape."""
+    from oracle import mpo as OM
+    from oracle import tdvp as T
+    Hw = OM.hamiltonian_mpo(wl.model)
+    rng = np.random.default_rng(0)
+    cz = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)
+
+    def timed(f):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            f()
+            n += 1
+            el = time.perf_counter() - t0
+            if el > rep_s or n >= 3:
+                return el / n
+
+    cache = {}
+    t_step, n_shapes, t_sample = 0.0, 0, time.perf_counter()
+    for bonds in states:
+        L = len(Hw)
+        for i in range(L):
+            W = Hw[i]
+            d = W.shape[2]
+            a = 1 if i == 0 else bonds[i - 1]
+            b = 1 if i == L - 1 else bonds[i]
+            key = (a, b, W.shape)
+            if key not in cache:
+                Le, Re, A = cz(W.shape[0], a, a), cz(W.shape[1], b, b), cz(a, d, d, b)
+                C = cz(b, b)
+                t_h = timed(lambda: T.heff_apply(Le, W, Re, A))
+                t_q = timed(lambda: T.qr_pos(A.reshape(a * d * d, b)))
+                t_e = timed(lambda: T.left_env(Le, A, W, A))
+                t_k = timed(lambda: T.keff_apply(cz(W.shape[1], b, b), Re, C)) if i < L - 1 else 0.0
+                cache[key] = (t_h, t_q, t_e, t_k)
+                n_shapes += 1
+            t_h, t_q, t_e, t_k = cache[key]
+            t_step += 2 * (krylov_mean * (t_h + t_k) + t_q + t_e) + t_e / len(states)
+    el = time.perf_counter() - t_sample
+    cores, blas = blas_info()
+    return {"value": 1.0 / t_step, "unit": "pair-steps/s", "cores": cores, "kind": "oracle",
+            "blas": blas, "seconds_per_pair_step": t_step,
+            "sample": f"oracle H_eff, K_eff, environment and QR kernels timed at each of the "
+                      f"{n_shapes} distinct site shapes of the two prepared states "
+                      f"({el:.1f} s of CPU work), assembled into one pair-step with "
+                      f"{krylov_mean:.2f} Krylov vectors per exponential (the GPU run's mean)"}
+
+
+def c_err(C, ref, c0):
+    """err_C = max_k |C_k - C_ref_k| / |C_ref(0)|."""
+    return float(np.abs(np.asarray(C) - np.asarray(ref)).max() / abs(c0))
+
+
+def mu_window(C, dt, beta, c0):
+    """Kubo integral (beta / e0) int Re C dt over the timed window (trapezoid,
+    C(0) = c0 first), e0 = 1."""
+    c = np.concatenate([[c0], np.asarray(C)])
+    return float(beta * dt * (c.real.sum() - 0.5 * (c[0].real + c[-1].real)))
+
+
+def roofline_entries(st, peak_of_kind):
+    out = []
+    for k in range(32):
+        n = st["kind_launches"][k]
+        if n == 0 or st["kind_ms"][k] <= 0:
+            continue
+        ach = st["kind_flops"][k] / st["kind_ms"][k] / 1e9
+        peak = peak_of_kind(k)
+        out.append({"kernel": kernel_name(k), "launches": n,
+                    "avg_launch_ms": st["kind_ms"][k] / n,
+                    "achieved": ach, "peak": peak, "frac": ach / peak,
+                    "algorithmic_flops_per_launch": st["kind_flops"][k] / n,
+                    "algorithmic_bytes_per_launch": st["kind_bytes"][k] / n})
+    return sorted(out, key=lambda e: -e["avg_launch_ms"] * e["launches"])
 
 
 def main():
@@ -236,22 +302,23 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="headline")
-    ap.add_argument("--precision", default="c64", choices=["c64", "c128"],
-                    help="contraction precision of the timed steps (c128: the FP64 path)")
+    ap.add_argument("--compare-steps", type=int, default=10,
+                    help="steps of the bf16x3 and float64 comparison runs (at most --steps)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
+    ap.add_argument("--no-bf16x3", action="store_true", help="skip the bf16x3 run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-grow", type=int, default=None,
                     help="growth steps of the preparation (default: the workload's; <0 adaptive)")
+    ap.add_argument("--expand-tol", type=float, default=None,
+                    help="bond expansion threshold of the preparation's TDVP steps "
+                         "(default: the workload's; 0 turns expansion off)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device inside its own "
                          "profiler region (HBM counter calibration)")
     ap.add_argument("--verbose", type=int, default=1,
                     help="library progress lines on stderr (0 silent, 2 per compression)")
-    ap.add_argument("--expand-tol", type=float, default=None,
-                    help="bond expansion threshold of the preparation's TDVP steps "
-                         "(default: the workload's; 0 turns expansion off)")
     ap.add_argument("--krylov-tol", type=float, default=None,
-                    help="Lanczos stop tolerance (default: the workload's)")
+                    help="Lanczos stop tolerance of the mixed runs (default: the workload's)")
     ap.add_argument("--summarize", nargs=3, metavar=("KIND", "CSV", "LOG"),
                     help="summarise rocprofv3 CSV rows (KIND trace or pmc) of the timed window "
                          "recorded in LOG, then exit (no GPU)")
@@ -272,18 +339,19 @@ def main():
     m, r = wl.model, wl.run
     if args.n_grow is not None:
         r.n_grow = args.n_grow
+    if args.expand_tol is not None:
+        r.expand_tol = args.expand_tol
     ctx = api.Context(0)
     ctx.set_verbose(args.verbose)
     H, J = api.mpo_build(ctx, m)
     tol = args.krylov_tol if args.krylov_tol is not None else r.krylov_tol
     mmax = r.krylov_mmax
 
-    log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D})")
+    log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D}, "
+        f"{wl.precision} contractions, expansion {r.expand_tol:g})")
     t0 = time.perf_counter()
-    if args.expand_tol is not None:
-        r.expand_tol = args.expand_tol
     psi_beta, logz = api.thermal_prep(ctx, H, r.beta, r.n_imag, r.n_grow, r.D, cutoff=r.cutoff,
-                                      precision=args.precision, tol=tol, mmax=mmax,
+                                      precision=wl.precision, tol=tol, mmax=mmax,
                                       expand_tol=r.expand_tol)
     t_prep = time.perf_counter() - t0
     bonds = psi_beta.info()["bond_dims"]
@@ -296,6 +364,7 @@ def main():
     log(f"[bench] j|Psi> compressed in {t_j:.1f} s, bonds max {max(pbonds)} "
         f"mean {sum(pbonds) / len(pbonds):.1f}")
     psi0 = psi_beta
+    c0 = api.overlap(ctx, psi0, J, phi0)
 
     # warmup (untimed), then the timed mixed-precision steps
     if args.warmup:
@@ -309,58 +378,88 @@ def main():
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         roctx.resume()
-        c0 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
+        c0t = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
         dst.copy_(src)
         torch.cuda.synchronize()
-        c1 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
+        c1t = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
         roctx.pause()
-        log(f"[bench] calibration copy of {n * 4} bytes boottime_ns {c0} {c1}")
+        log(f"[bench] calibration copy of {n * 4} bytes boottime_ns {c0t} {c1t}")
         del src, dst
     sps = args.steps / el_mix
     log(f"[bench] mixed: {el_mix / args.steps * 1e3:.1f} ms/step, H_eff "
         f"{st['heff_flops'] / max(st['heff_ms'], 1e-9) / 1e9:.1f} TFLOP/s")
 
+    peak_of_kind = lambda k: {0: PEAK["c128"], 1: PEAK["c64"], 2: PEAK["bf16"]}[k >> 3]
     out = {
         "metric": METRIC, "value": sps, "unit": "pair-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el_mix / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.precision, "data": "synthetic",
+        "dtype": wl.precision, "data": "synthetic",
         "config": {"workload": wl.name, "n_mol": m.n_mol, "local_modes": m.n_loc,
                    "bond_modes": m.n_nl, "levels": m.levels_loc, "D": r.D,
-                   "T_K": 300.0, "dt_fs": 0.5, "krylov_tol": tol, "n_imag": r.n_imag,
-                   "n_grow": r.n_grow, "psi_bond_max": max(bonds),
+                   "T_K": r.T_K, "dt_fs": r.dt_fs, "krylov_tol": tol, "n_imag": r.n_imag,
+                   "n_grow": r.n_grow, "expand_tol": r.expand_tol,
+                   "psi_bond_max": max(bonds),
                    "psi_bond_mean": round(sum(bonds) / len(bonds), 1),
                    "phi_bond_max": max(pbonds), "phi_bond_mean": round(sum(pbonds) / len(pbonds), 1)},
         "heff_tflops": st["heff_flops"] / max(st["heff_ms"], 1e-9) / 1e9,
+        "whole_step_tflops": st["all_flops"] / el_mix / 1e12,
         "matvecs_per_step": st["matvecs"] / args.steps,
         "krylov_mean": st["krylov_vectors"] / max(st["expm_calls"], 1),
         "prep_s": t_prep, "jcompress_s": t_j,
     }
+    dom = st["dom_kind"]
     dom_avg_ms = st["dom_ms"] / max(st["dom_launches"], 1)
     achieved = st["dom_flops"] / max(st["dom_ms"], 1e-12) / 1e9     # TFLOP/s
-    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision],
-                       "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
-                       "traffic": measured_traffic(kernel_name(st["dom_kind"]), wl.name),
-                       "kernel": kernel_name(st["dom_kind"]),
+    peak = peak_of_kind(dom)
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak,
+                       "unit": "TFLOP/s", "frac": achieved / peak,
+                       "traffic": measured_traffic(kernel_name(dom), wl.name),
+                       "kernel": kernel_name(dom),
                        "avg_launch_ms": dom_avg_ms, "launches": st["dom_launches"],
                        "algorithmic_bytes_per_launch":
                            st["dom_bytes"] / max(st["dom_launches"], 1),
                        "algorithmic_flops_per_launch":
-                           st["dom_flops"] / max(st["dom_launches"], 1)}
+                           st["dom_flops"] / max(st["dom_launches"], 1),
+                       "mfma_executed_frac": achieved / peak * (0.75 if dom >> 3 == 1 else 1.0)}
+    out["roofline_all"] = roofline_entries(st, peak_of_kind)
+    ncmp = max(1, min(args.compare_steps, args.steps))
+    refs = {}
     if not args.no_fp64:
         C64, el64, st64 = run_steps(api, ctx, H, J, _as(api, ctx, psi0, "c128"),
-                                    _as(api, ctx, phi0, "c128"), args.steps, r.dt, 1e-12,
-                                    mmax, True)
-        out["fp64_steps_per_s"] = args.steps / el64
+                                    _as(api, ctx, phi0, "c128"), ncmp, r.dt, 1e-14, mmax, True)
+        refs["c128"] = C64
+        out["fp64_steps_per_s"] = ncmp / el64
         out["speedup_vs_fp64"] = sps / out["fp64_steps_per_s"]
         out["fp64_heff_tflops"] = st64["heff_flops"] / max(st64["heff_ms"], 1e-9) / 1e9
-        out["c_rel_err_vs_fp64"] = float(np.abs(C_mix - C64).max() /
-                                         abs(api.overlap(ctx, psi0, J, phi0)))
-        log(f"[bench] fp64: {el64 / args.steps * 1e3:.1f} ms/step; C(t) rel err "
-            f"{out['c_rel_err_vs_fp64']:.2e}")
+        out["c_rel_err_vs_fp64"] = c_err(C_mix[:ncmp], C64, c0)
+        mu64 = mu_window(C64, r.dt, r.beta, c0)
+        out["mu_rel_err_vs_fp64"] = abs(mu_window(C_mix[:ncmp], r.dt, r.beta, c0) - mu64) / abs(mu64)
+        out["compare_steps"] = ncmp
+        log(f"[bench] fp64 (Krylov tol 1e-14): {el64 / ncmp * 1e3:.1f} ms/step; C(t) rel err "
+            f"{out['c_rel_err_vs_fp64']:.2e} over {ncmp} steps")
+    if not args.no_bf16x3:
+        Cb, elb, stb = run_steps(api, ctx, H, J, _as(api, ctx, psi0, "bf16x3"),
+                                 _as(api, ctx, phi0, "bf16x3"), ncmp, r.dt, tol, mmax, True)
+        bx = {"steps_per_s": ncmp / elb, "ms_per_step": elb / ncmp * 1e3,
+              "heff_tflops": stb["heff_flops"] / max(stb["heff_ms"], 1e-9) / 1e9,
+              "whole_step_tflops": stb["all_flops"] / elb / 1e12,
+              "roofline_all": roofline_entries(stb, peak_of_kind)}
+        if "c128" in refs:
+            bx["c_rel_err_vs_fp64"] = c_err(Cb, refs["c128"], c0)
+            mu64 = mu_window(refs["c128"], r.dt, r.beta, c0)
+            bx["mu_rel_err_vs_fp64"] = abs(mu_window(Cb, r.dt, r.beta, c0) - mu64) / abs(mu64)
+            bx["speedup_vs_fp64"] = bx["steps_per_s"] / out["fp64_steps_per_s"]
+        out["bf16x3"] = bx
+        log(f"[bench] bf16x3: {bx['ms_per_step']:.1f} ms/step")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, out["matvecs_per_step"])
+        states = [bonds, pbonds]
+        out["cpu_baseline"] = cpu_baseline(wl, states, out["krylov_mean"])
+    ctx.synchronize()
     print(json.dumps(out), flush=True)
+    # release every device handle and the context before interpreter exit
+    del psi_beta, phi0, psi0, H, J
+    ctx.close()
 
 
 def _as(api, ctx, psi, precision):

@@ -133,8 +133,18 @@ typedef struct {
     int64_t expm_calls;
     int64_t krylov_max;
     int32_t dom_kind;          /* identity of that kernel: 8*precision (0 f64,
-                                  1 f32) + 4*(f64 output) + 2*(A k-contiguous)
-                                  + (B k-contiguous) */
+                                  1 f32, 2 bf16x3) + 4*(f64 output)
+                                  + 2*(A k-contiguous) + (B k-contiguous) */
+    double all_flops;          /* algorithmic flops (8 m n k per complex
+                                  product) of every contraction launched,
+                                  timed or not: matvecs, environments,
+                                  overlaps, gauge and compression GEMMs */
+    /* per kernel identity (index = dom_kind's encoding): the device-timed
+     * H_eff / K_eff launches of that instance, as for dom_* */
+    int64_t kind_launches[32];
+    double kind_ms[32];
+    double kind_flops[32];
+    double kind_bytes[32];
 } ftd_stats;
 ftd_status ftd_ctx_set_timing(ftd_ctx* ctx, int32_t enable);
 ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out);

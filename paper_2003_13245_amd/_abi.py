@@ -47,7 +47,9 @@ class Stats(C.Structure):
                 ("dom_ms", C.c_double), ("dom_flops", C.c_double), ("dom_bytes", C.c_double),
                 ("matvecs", C.c_int64), ("krylov_vectors", C.c_int64),
                 ("expm_calls", C.c_int64), ("krylov_max", C.c_int64),
-                ("dom_kind", C.c_int32)]
+                ("dom_kind", C.c_int32), ("all_flops", C.c_double),
+                ("kind_launches", C.c_int64 * 32), ("kind_ms", C.c_double * 32),
+                ("kind_flops", C.c_double * 32), ("kind_bytes", C.c_double * 32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

@@ -133,7 +133,11 @@ class Context:
     def stats(self) -> dict:
         s = _abi.Stats()
         check(lib.ftd_ctx_stats(self.h, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in _abi.Stats._fields_}
+        out = {}
+        for k, _ in _abi.Stats._fields_:
+            v = getattr(s, k)
+            out[k] = list(v) if k.startswith("kind_") else v
+        return out
 
 
 class _Handle:

@@ -194,13 +194,14 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
             s.krylov_vectors += a.krylov_vectors;
             s.expm_calls += a.expm_calls;
             s.krylov_max = std::max(s.krylov_max, a.krylov_max);
+            s.all_flops += a.all_flops;
         }
         s.heff_launches = 0;
         s.heff_ms = 0;
         s.heff_flops = 0;
         // per kernel identity totals, over both streams
-        std::vector<double> kms(64, 0.0), kfl(64, 0.0), kby(64, 0.0);
-        std::vector<int64_t> kn(64, 0);
+        std::vector<double> kms(32, 0.0), kfl(32, 0.0), kby(32, 0.0);
+        std::vector<int64_t> kn(32, 0);
         // device timestamps of the timed GEMM launches, per context
         int rate_khz = 0;
         FTD_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c.device));
@@ -242,7 +243,7 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
                 } else if (e.m) {
                     FTD_HIP(hipEventElapsedTime(&kms_one, e.a, e.m));
                 }
-                const int k = e.kind & 63;
+                const int k = e.kind & 31;
                 kms[k] += kms_one;
                 kfl[k] += e.flops;
                 kby[k] += e.bytes;
@@ -250,8 +251,14 @@ ftd_status ftd_ctx_stats(ftd_ctx* ctx, ftd_stats* out) {
             }
         }
         int best = 0;
-        for (int k = 1; k < 64; ++k)
+        for (int k = 1; k < 32; ++k)
             if (kms[k] > kms[best]) best = k;
+        for (int k = 0; k < 32; ++k) {
+            s.kind_launches[k] = kn[k];
+            s.kind_ms[k] = kms[k];
+            s.kind_flops[k] = kfl[k];
+            s.kind_bytes[k] = kby[k];
+        }
         s.dom_launches = kn[best];
         s.dom_ms = kms[best];
         s.dom_flops = kfl[best];

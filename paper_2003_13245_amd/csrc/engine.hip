@@ -687,12 +687,14 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
     const int hint = std::max(1, last - 1);
     std::vector<size_t> ev_mark(kmax + 1);
     std::vector<int64_t> mv_mark(kmax + 1);
+    std::vector<double> fl_mark(kmax + 1);
     ctx->kstop = kd.flag + 3;
     int done = 0;
     try {
         for (int k = 0; k < kmax; ++k) {
             ev_mark[k] = ctx->events.size();
             mv_mark[k] = ctx->stats.matvecs;
+            fl_mark[k] = ctx->stats.all_flops;
             double* vk = V + (int64_t)k * vs;
             double* w = V + (int64_t)(k + 1) * vs;
             op(vk, w);
@@ -727,6 +729,7 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
     if (m < done) {
         ctx->events.resize(ev_mark[m]);
         ctx->stats.matvecs = mv_mark[m];
+        ctx->stats.all_flops = fl_mark[m];
     }
     k_lincomb(ctx, V, vs, m, kd.u, kd.nrm + 1, x, n, n);
     last = m;

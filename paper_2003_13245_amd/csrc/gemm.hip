@@ -582,6 +582,11 @@ void gemm(Ctx* ctx, Prec prec, bool out_f64, const void* A, const void* B, void*
         return;
     }
     const int tm = (p.M + GBM - 1) / GBM, tn = (p.N + GBN - 1) / GBN;
+    {
+        double terms = 0;
+        for (int i = 0; i < p.nprob; ++i) terms += p.prob[i].t1 - p.prob[i].t0;
+        ctx->stats.all_flops += 8.0 * p.M * (double)p.N * p.K * terms;
+    }
     p.ksplit = ks;
     p.stop = ctx->kstop;
     size_t esz = (prec == Prec::F64) ? sizeof(double) : sizeof(float);

@@ -110,6 +110,8 @@ class Run:
     krylov_mmax: int = 40
     cutoff: float = 1e-10  # relative singular-value cutoff for compression
     expand_tol: float = 0.0  # bond expansion threshold of the one-site TDVP steps (0: off)
+    T_K: float = 0.0     # temperature in kelvin (0: model units, beta given directly)
+    dt_fs: float = 0.0   # real-time step in femtoseconds (0: model units)
 
 
 @dataclasses.dataclass
@@ -184,7 +186,7 @@ def rubrene_shaped(n_mol=21, n_loc=4, n_nl=1, levels=10, D=128, T=300.0,
     n_steps = int(round(t_fs / dt_fs))
     r = Run(beta=beta, n_imag=n_imag, n_grow=1, D=D, dt=dt, n_steps=n_steps,
             krylov_tol=1e-14 if precision == "c128" else 1e-8,
-            expand_tol=1e-8 if precision == "c128" else 1e-5)
+            expand_tol=1e-8 if precision == "c128" else 1e-5, T_K=T, dt_fs=dt_fs)
     name = f"hp_n{n_mol}_loc{n_loc}_nl{n_nl}_d{levels}_D{D}_T{T:g}"
     return Workload(name, m, r, precision)
 
@@ -200,7 +202,7 @@ def adjoint_chain() -> Workload:
     m = Model(n_mol=11, periodic=1, omega_loc=omega, g_loc=g, omega_nl=[],
               g_nl=[], levels_loc=8, levels_nl=1, V=mev(80.0))
     r = Run(beta=beta_of_T(300.0), n_imag=40, n_grow=1, D=64, dt=fs(0.5),
-            n_steps=100)
+            n_steps=100, T_K=300.0, dt_fs=0.5)
     return Workload("holstein_n11_loc3_d8_D64_T300", m, r, "c128")
 
 

@@ -24,14 +24,53 @@ def test_kernel_name_codes(bench):
     assert bench.kernel_name(1 * 8 + 4 + 2 + 1) == "ftd::gemm_kernel<float, double, true, true>"
     assert bench.kernel_name(1 * 8 + 2) == "ftd::gemm_kernel<float, float, true, false>"
     assert bench.kernel_name(0 * 8 + 4 + 1) == "ftd::gemm_kernel<double, double, false, true>"
+    assert bench.kernel_name(2 * 8 + 4 + 2 + 1) == "ftd::gemm_bx3_kernel<double, true, true>"
+
+
+def test_error_and_window_mobility(bench):
+    import numpy as np
+    ref = np.array([1.0 + 0.1j, 0.5, 0.25])
+    C = ref + np.array([0.0, 1e-5, -2e-5j])
+    assert bench.c_err(C, ref, 2.0) == pytest.approx(1e-5)
+    # trapezoid of Re C over [0, 3 dt] with C(0) = c0 prepended
+    mu = bench.mu_window(ref, 0.5, 2.0, 2.0)
+    assert mu == pytest.approx(2.0 * 0.5 * (1.0 + 1.0 + 0.5 + 0.125))
+
+
+def test_roofline_entries(bench):
+    st = {k: [0] * 32 for k in ("kind_launches", "kind_ms", "kind_flops", "kind_bytes")}
+    st["kind_launches"][13], st["kind_ms"][13], st["kind_flops"][13] = 10, 2.0, 1.5e11
+    st["kind_launches"][10], st["kind_ms"][10], st["kind_flops"][10] = 4, 1.0, 5e10
+    out = bench.roofline_entries(st, lambda k: 157.3)
+    assert [e["kernel"] for e in out] == ["ftd::gemm_kernel<float, double, false, true>",
+                                          "ftd::gemm_kernel<float, float, true, false>"]
+    assert out[0]["achieved"] == pytest.approx(75.0) and out[0]["avg_launch_ms"] == 0.2
+    assert out[1]["frac"] == pytest.approx(50.0 / 157.3)
+
+
+def test_cpu_baseline_assembles_a_step(bench):
+    """Every distinct site shape is timed once and the step is the sum over
+    both states' sites; a larger Krylov count can only make it slower."""
+    from paper_2003_13245_amd import workloads as W
+    from oracle import model as Mdl
+    wl = W.rubrene_shaped(n_mol=3, n_loc=1, n_nl=1, levels=3, D=6)
+    L = len(Mdl.site_dims(wl.model))
+    bonds = [min(6, 4 ** (i + 1), 4 ** (L - 1 - i)) for i in range(L - 1)]
+    a = bench.cpu_baseline(wl, [bonds, bonds], 4.0, rep_s=0.01)
+    b = bench.cpu_baseline(wl, [bonds, bonds], 8.0, rep_s=0.01)
+    assert a["kind"] == "oracle" and a["unit"] == "pair-steps/s" and a["cores"] >= 1
+    assert a["value"] > 0 and b["seconds_per_pair_step"] > a["seconds_per_pair_step"] * 1.2
 
 
 def test_traffic_record_matches_current_source(bench):
     path = os.path.join(ROOT, "profiles", "traffic_hp_n21_loc4_nl1_d10_D128_T300.json")
     rec = json.load(open(path))
     t = bench.measured_traffic(rec["kernel"], rec["workload"])
-    # the committed record was taken with the committed GEMM source
-    assert t is not None and t == pytest.approx(rec["traffic_bytes_per_launch"])
+    if rec["gemm_source_sha256"] == bench.gemm_source_sha256():
+        assert t is not None and t == pytest.approx(rec["traffic_bytes_per_launch"])
+    else:
+        # counters taken with another GEMM source are not reported
+        assert t is None
     # its own arithmetic: counters in KiB, scaled by the copy calibration
     fb = rec["fetch_size_kib_in_window"] * 1024 * rec["fetch_factor"] / rec["dispatches_in_window"]
     wb = rec["write_size_kib_in_window"] * 1024 * rec["write_factor"] / rec["dispatches_in_window"]
