@@ -36,7 +36,8 @@ def _release_all():
 
 __all__ = ["Context", "Mpo", "Mps", "mpo_build", "thermal_prep", "tdvp_step", "tdvp_step_expand",
            "tdvp_pair",
-           "corr_current", "mobility", "mobility_sweep", "mobility_grad", "mean_free_path", "fgr_corr", "reduced_density",
+           "corr_current", "mobility", "mobility_sweep", "mobility_grad", "mobility_autograd",
+           "Mobility", "mean_free_path", "fgr_corr", "reduced_density",
            "coherent_length", "qr", "apply_compress", "overlap", "heff_apply", "mps_from_host",
            "mps_load", "gemm", "FtdError"]
 
@@ -384,6 +385,66 @@ def mobility_grad(ctx, model, beta, n_imag, n_grow, D, dt, n_steps, cutoff=1e-10
     grads = {"omega_loc": out["omega_loc"][:nl], "g_loc": out["g_loc"][:nl],
              "omega_nl": out["omega_nl"][:nn], "g_nl": out["g_nl"][:nn]}
     return mu.value, grads
+
+
+def mobility_autograd(ctx, model, beta, omega_loc, g_loc, omega_nl, g_nl, n_imag, n_grow, D,
+                      dt, n_steps, cutoff=1e-10, precision="c128", tol=1e-14, mmax=40,
+                      rel_step=1e-4):
+    """The mobility (a.u.) as a differentiable function of the shared mode
+    frequencies and couplings, given as torch tensors (float64, CPU; empty
+    tensors where the model has no such modes).  The forward pass runs
+    ftd_mobility_grad: mu and its gradient, by central finite differences
+    through the whole GPU path (relative step rel_step); backward scales that
+    gradient by the incoming mu-bar, so the isotope derivative or any chain
+    through omega(m), g(m) follows from torch's autograd."""
+    return Mobility.apply(omega_loc, g_loc, omega_nl, g_nl, ctx, model, beta,
+                          (n_imag, n_grow, D, dt, n_steps, cutoff, precision, tol, mmax,
+                           rel_step))
+
+
+def _mobility_function():
+    import torch
+
+    class _Mobility(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, omega_loc, g_loc, omega_nl, g_nl, ctx, model, beta, run):
+            import dataclasses
+            (n_imag, n_grow, D, dt, n_steps, cutoff, precision, tol, mmax, rel_step) = run
+            m = dataclasses.replace(
+                model, omega_loc=omega_loc.detach().double().tolist(),
+                g_loc=g_loc.detach().double().tolist(),
+                omega_nl=omega_nl.detach().double().tolist(),
+                g_nl=g_nl.detach().double().tolist())
+            mu, gr = mobility_grad(ctx, m, beta, n_imag, n_grow, D, dt, n_steps, cutoff=cutoff,
+                                   precision=precision, tol=tol, mmax=mmax, rel_step=rel_step)
+            grads = [torch.as_tensor(np.asarray(gr[k], dtype=np.float64)).reshape(t.shape)
+                     for k, t in (("omega_loc", omega_loc), ("g_loc", g_loc),
+                                  ("omega_nl", omega_nl), ("g_nl", g_nl))]
+            fctx.save_for_backward(*grads)
+            return torch.tensor(mu, dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, mu_bar):
+            gw, gg, gwn, ggn = fctx.saved_tensors
+            return (mu_bar * gw, mu_bar * gg, mu_bar * gwn, mu_bar * ggn,
+                    None, None, None, None)
+
+    return _Mobility
+
+
+class _LazyMobility:
+    """torch.autograd.Function of the mobility (see mobility_autograd),
+    created on first use so that importing the binding does not need torch's
+    autograd machinery."""
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyMobility._fn is None:
+            _LazyMobility._fn = _mobility_function()
+        return _LazyMobility._fn.apply(*args)
+
+
+Mobility = _LazyMobility()
 
 
 def reduced_density(ctx, model, psi):

@@ -154,6 +154,11 @@ void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double*
 // w -= sum_j V_j h[j] and out[0] = |w|^2 in one pass
 void k_multiaxpy_nrm2(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
                       double* w, int64_t n, int64_t plane, double* out);
+// w -= sum_j V_j h[j], then h[j] = <V_j, w> of the updated w, in one pass over
+// V and w; false (nothing done) when k or n is outside its range (k <= 16,
+// long vectors), so that the caller falls back to k_multiaxpy + k_multidot
+bool k_multiaxpy_dot(Ctx* ctx, const double* V, int64_t vstride, int k, double* h, double* w,
+                     int64_t n, int64_t plane);
 // w -= sum_j V_j h[j]
 void k_multiaxpy(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h, double* w,
                  int64_t n, int64_t plane);

@@ -698,9 +698,12 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
             double* vk = V + (int64_t)k * vs;
             double* w = V + (int64_t)(k + 1) * vs;
             op(vk, w);
-            k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h, kd.alpha + k);   // alpha_k = <v_k, w>
-            k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
-            k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
+            // classical Gram-Schmidt twice; alpha_k = <v_k, w> of the first pass
+            k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h, kd.alpha + k);
+            if (!k_multiaxpy_dot(ctx, V, vs, k + 1, kd.h, w, n, n)) {
+                k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
+                k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
+            }
             k_multiaxpy_nrm2(ctx, V, vs, k + 1, kd.h, w, n, n, kd.nrm);
             const int exhausted = (k + 1 == n) ? 1 : 0;
             k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted);

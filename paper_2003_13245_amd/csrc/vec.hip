@@ -181,6 +181,96 @@ void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out) {
     FTD_HIP(hipGetLastError());
 }
 
+// Several complex dot products per thread with one read of w: vectors
+// V_j0 .. V_j0+kc-1 (kc <= KC), block partials into part[(j * nb + b) * 2].
+template <int KC>
+__device__ __forceinline__ void block_sums_out(double (&sr)[KC], double (&si)[KC], int kc, int j0,
+                                               double* __restrict__ part, double* sh) {
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        if (j >= kc) break;
+        const double a = block_sum(sr[j], sh), b = block_sum(si[j], sh);
+        if (threadIdx.x == 0) {
+            const int64_t o = ((int64_t)(j0 + j) * gridDim.x + blockIdx.x) * 2;
+            part[o] = a;
+            part[o + 1] = b;
+        }
+    }
+}
+
+template <int KC>
+__global__ __launch_bounds__(RB) void multidot_w1_partial(const double* __restrict__ V,
+                                                         int64_t vstride, int j0, int kc,
+                                                         const double* __restrict__ w, int64_t n,
+                                                         int64_t plane, double* __restrict__ part,
+                                                         const int* stop) {
+    if (stop && *stop) return;
+    __shared__ double sh[16];
+    double sr[KC], si[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) sr[j] = si[j] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double wr = w[i], wi = w[i + plane];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            if (j < kc) {
+                const double* v = V + (int64_t)(j0 + j) * vstride;
+                const double vr = v[i], vi = v[i + plane];
+                sr[j] += vr * wr + vi * wi;
+                si[j] += vr * wi - vi * wr;
+            }
+        }
+    }
+    block_sums_out<KC>(sr, si, kc, j0, part, sh);
+}
+
+// One pass of w -= sum_j V_j h[j] (j < k <= KC) that also forms the block
+// partials of the next projections <V_j, w> of the updated w (the second
+// Gram-Schmidt pass needs exactly these), part[(j * nb + b) * 2].
+template <int KC>
+__global__ __launch_bounds__(RB) void multiaxpy_dot_partial(const double* __restrict__ V,
+                                                           int64_t vstride, int k,
+                                                           const double* __restrict__ h,
+                                                           double* __restrict__ w, int64_t n,
+                                                           int64_t plane,
+                                                           double* __restrict__ part,
+                                                           const int* stop) {
+    if (stop && *stop) return;
+    __shared__ double sh[16];
+    double hr[KC], hi[KC], sr[KC], si[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        hr[j] = j < k ? h[2 * j] : 0.0;
+        hi[j] = j < k ? h[2 * j + 1] : 0.0;
+        sr[j] = si[j] = 0.0;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double vr[KC], vi[KC];
+        double ar = w[i], ai = w[i + plane];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            if (j < k) {
+                vr[j] = V[(int64_t)j * vstride + i];
+                vi[j] = V[(int64_t)j * vstride + i + plane];
+                ar -= vr[j] * hr[j] - vi[j] * hi[j];
+                ai -= vr[j] * hi[j] + vi[j] * hr[j];
+            }
+        }
+        w[i] = ar;
+        w[i + plane] = ai;
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            if (j < k) {
+                sr[j] += vr[j] * ar + vi[j] * ai;
+                si[j] += vr[j] * ai - vi[j] * ar;
+            }
+        }
+    }
+    block_sums_out<KC>(sr, si, k, 0, part, sh);
+}
+
 // h[j] = <V_j, w>: grid (nb, k)
 __global__ void multidot_partial(const double* __restrict__ V, int64_t vstride,
                                  const double* __restrict__ w, int64_t n, int64_t plane,
@@ -207,14 +297,38 @@ __global__ void multidot_partial(const double* __restrict__ V, int64_t vstride,
 void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double* w, int64_t n,
                 int64_t plane, double* h, double* alpha) {
     if (k <= 0) return;
-    int nb = red_blocks(n);
-    nb = std::min(nb, 128);
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
-    multidot_partial<<<dim3(nb, k), RB, 0, ctx->stream>>>(V, vstride, w, n, plane, part,
-                                                          ctx->kstop);
+    int nb = red_blocks(n);
+    if (n >= (int64_t)RB * 64) {
+        // long vectors: w read once per chunk of eight Krylov vectors
+        for (int j0 = 0; j0 < k; j0 += 8)
+            multidot_w1_partial<8><<<nb, RB, 0, ctx->stream>>>(V, vstride, j0, std::min(8, k - j0),
+                                                               w, n, plane, part, ctx->kstop);
+    } else {
+        nb = std::min(nb, 128);
+        multidot_partial<<<dim3(nb, k), RB, 0, ctx->stream>>>(V, vstride, w, n, plane, part,
+                                                              ctx->kstop);
+    }
     sum_partials<<<k, RB, 0, ctx->stream>>>(part, nb, 2, h, ctx->kstop, alpha, k - 1);
     FTD_HIP(hipGetLastError());
+}
+
+bool k_multiaxpy_dot(Ctx* ctx, const double* V, int64_t vstride, int k, double* h, double* w,
+                     int64_t n, int64_t plane) {
+    if (k <= 0 || k > 16 || n < (int64_t)RB * 64) return false;
+    ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
+    double* part = ctx->ws_red.as<double>();
+    const int nb = red_blocks(n);
+    if (k <= 8)
+        multiaxpy_dot_partial<8><<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
+                                                             ctx->kstop);
+    else
+        multiaxpy_dot_partial<16><<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
+                                                              ctx->kstop);
+    sum_partials<<<k, RB, 0, ctx->stream>>>(part, nb, 2, h, ctx->kstop);
+    FTD_HIP(hipGetLastError());
+    return true;
 }
 
 // w -= sum_j V_j h[j], then block partials of |w|^2 (one pass over w)

@@ -54,3 +54,26 @@ def test_gradient_rejects_bad_step(ctx):
     for step in (0.0, 0.5, float("nan")):
         with pytest.raises(api.FtdError):
             api.mobility_grad(ctx, m, 1.0, rel_step=step, **RUN)
+
+
+def test_mobility_autograd_function(ctx):
+    """torch autograd through the Mobility function: backward gives mu-bar
+    times ftd_mobility_grad's gradient, and the chain rule through
+    omega -> s omega, g -> g / sqrt(s) gives the frequency-scaling derivative
+    at s = 1, d mu / d s = sum_k omega_k dmu/domega_k - (1/2) sum_k g_k dmu/dg_k."""
+    import torch
+    from paper_2003_13245_amd import api
+    m = small_model(n_mol=3, n_loc=2, n_nl=0, levels=3)
+    mu_ref, gr = api.mobility_grad(ctx, m, 1.0, rel_step=1e-4, **RUN)
+    w0 = torch.tensor(m.omega_loc, dtype=torch.float64)
+    g0 = torch.tensor(m.g_loc, dtype=torch.float64)
+    s = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    empty = torch.zeros(0, dtype=torch.float64)
+    mu = api.mobility_autograd(ctx, m, 1.0, w0 * s, g0 / torch.sqrt(s), empty, empty,
+                               rel_step=1e-4, **RUN)
+    assert abs(mu.item() - mu_ref) <= 1e-12 * abs(mu_ref)
+    (2.5 * mu).backward()
+    expect = 2.5 * (float(np.dot(m.omega_loc, gr["omega_loc"]))
+                    - 0.5 * float(np.dot(m.g_loc, gr["g_loc"])))
+    say(f"[grad] autograd d(2.5 mu)/ds {s.grad.item():.12g}, expected {expect:.12g}")
+    assert abs(s.grad.item() - expect) <= 1e-10 * max(1.0, abs(expect))

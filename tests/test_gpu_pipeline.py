@@ -22,13 +22,15 @@ relative on the tiny ring), and at least 1e-3 relative.
 
 Floors per step k are running maxima of |C' - C| / |C(0)| over the oracle
 variants: a relative 1e-15 perturbation of the state; the other SVD driver;
-and every gauge QR factor perturbed by a relative delta, where delta is the
-measured distance between one GPU step and one oracle step from the same
-state (itself held below 1e-12).  The last variant is how the oracle itself
-amplifies differences of the size by which the two implementations differ
-per step (FP64 MFMA accumulation order, CholeskyQR against Householder QR,
-the Krylov stop test); several steps of these chains contain bursts that
-amplify them a hundredfold in one step.
+and every gauge QR factor perturbed by a fixed relative STEP_DELTA = 3e-14,
+the rounding level of one step of two float64 implementations fixed in
+advance (about 250 unit roundoffs: the dependent operations of one site
+update).  The last variant is how the oracle itself amplifies differences of
+the size by which two implementations differ per step (accumulation order,
+CholeskyQR against Householder QR, the Krylov stop test); several steps of
+these chains contain bursts that amplify them a hundredfold in one step.
+Every floor comes from oracle runs alone; the measured distance between one
+GPU step and one oracle step is reported and held below 1e-12 on its own.
 The GPU must satisfy err(k) <= max(1e-10, 30 x floor(k)) at every step."""
 import numpy as np
 import pytest
@@ -41,6 +43,11 @@ from oracle import tdvp as T
 from paper_2003_13245_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+# relative perturbation of every oracle gauge factor that stands for the
+# per-step rounding difference of two float64 implementations (fixed a
+# priori, not measured on the GPU)
+STEP_DELTA = 3e-14
 
 
 def say(*a):
@@ -110,9 +117,8 @@ class Case:
 
     def set_step_noise(self, delta):
         """Add the oracle's response to every gauge QR factor perturbed by a
-        relative `delta` (the measured one-step GPU/oracle difference, at
-        least 1e-15) to the floor."""
-        noise = max(1e-15, float(delta))
+        relative `delta` to the floor."""
+        noise = float(delta)
         if self.noise == noise:
             return
         T.QR_NOISE = noise
@@ -209,7 +215,8 @@ def test_corr_from_common_state(ctx, name):
     """C(t) on the GPU from the oracle's |Psi_beta>, against the oracle."""
     from paper_2003_13245_amd import api
     c = case(name)
-    c.set_step_noise(one_step_difference(ctx, c))
+    one_step_difference(ctx, c)
+    c.set_step_noise(STEP_DELTA)
     H, J = api.mpo_build(ctx, c.m)
     say(f"[e2e] {name}: gpu dynamics from the oracle state")
     psi = api.mps_from_host(ctx, c.psi.A)
@@ -228,7 +235,8 @@ def test_pipeline(ctx, name):
     own spread between the two SVD drivers, and never tighter than 1e-3."""
     from paper_2003_13245_amd import api
     c = case(name)
-    c.set_step_noise(one_step_difference(ctx, c))
+    one_step_difference(ctx, c)
+    c.set_step_noise(STEP_DELTA)
     say(f"[e2e] {name}: gpu pipeline")
     H, J, psi_g, _ = gpu_prep(ctx, c)
     C_g = api.corr_current(ctx, H, J, psi_g, c.r.D, c.r.dt, c.cfg["steps"], cutoff=c.cut)
