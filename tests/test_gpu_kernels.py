@@ -163,10 +163,23 @@ def test_tdvp_pair_matches_two_steps(ctx, kind):
         api.tdvp_pair(ctx, H, ga, ga, **kw)
 
 
-def test_unbuilt_precision_is_rejected(ctx):
-    from paper_2003_13245_amd import api
-    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2)
+def test_precisions_accepted_and_unknown_rejected(ctx):
+    """bf16x3 is a contraction precision like c64: one real-time TDVP step in
+    it stays within the split products' accuracy of the float64 step; an
+    unknown precision code is rejected with FTD_EINVAL."""
+    from paper_2003_13245_amd import _abi, api
+    m = small_model(n_mol=3, n_loc=1, n_nl=1, levels=3)
     dims = Mdl.site_dims(m)
-    g = api.mps_from_host(ctx, random_mps(dims, 3, np.random.default_rng(1), 0).A)
-    with pytest.raises(api.FtdError):
-        g.set_precision("bf16x3")
+    H, _ = api.mpo_build(ctx, m)
+    host = random_mps(dims, 8, np.random.default_rng(1), 0)
+    ref = api.mps_from_host(ctx, host.A)
+    low = api.mps_from_host(ctx, host.A)
+    low.set_precision("bf16x3")
+    assert low.info()["precision"] == 2
+    api.tdvp_step(ctx, H, ref, dt_real=0.1)
+    api.tdvp_step(ctx, H, low, dt_real=0.1, tol=1e-8)
+    d = mps_rel_distance(gpu_tensors(low, dims), gpu_tensors(ref, dims))
+    say(f"[prec] one bf16x3 step vs float64: {d:.1e}")
+    assert d < 1e-4
+    code = _abi.lib.ftd_mps_set_precision(low.h, 7)
+    assert code == _abi.FTD_EINVAL

@@ -22,10 +22,9 @@ relative on the tiny ring), and at least 1e-3 relative.
 
 Floors per step k are running maxima of |C' - C| / |C(0)| over the oracle
 variants: a relative 1e-15 perturbation of the state; the other SVD driver;
-and every gauge QR factor perturbed by a fixed relative STEP_DELTA = 3e-14,
+and every gauge QR factor perturbed by a fixed relative STEP_DELTA = 1e-13,
 the rounding level of one step of two float64 implementations fixed in
-advance (about 250 unit roundoffs: the dependent operations of one site
-update).  The last variant is how the oracle itself amplifies differences of
+advance (about 1000 unit roundoffs: the dependent operations of a sweep).  The last variant is how the oracle itself amplifies differences of
 the size by which two implementations differ per step (accumulation order,
 CholeskyQR against Householder QR, the Krylov stop test); several steps of
 these chains contain bursts that amplify them a hundredfold in one step.
@@ -47,7 +46,7 @@ pytestmark = pytest.mark.gpu
 # relative perturbation of every oracle gauge factor that stands for the
 # per-step rounding difference of two float64 implementations (fixed a
 # priori, not measured on the GPU)
-STEP_DELTA = 3e-14
+STEP_DELTA = 1e-13
 
 
 def say(*a):
