@@ -287,231 +287,200 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_lds_kernel(double* G, d
     }
 }
 
-// Blocked variant of chol_inv_lds_kernel for 16 <= n <= 128, same contract
-// and packed LDS layout, 1024 threads (four wavefronts per SIMD hide the LDS
-// latency that bounds a single 256-thread workgroup), two workgroup barriers
-// per block of kCholBlk columns:
-//  factor, per block K: waves 0 and 1 factor the diagonal block in registers
-//    (lane = 8 r + c, pivots and rows exchanged by shuffles) and solve the
-//    block row R_KJ = R_KK^{-H} G_KJ, one column per lane; then every thread
-//    applies the rank-kCholBlk update G_JJ' -= R_KJ^H R_KJ' with its row's
-//    factors cached in registers;
-//  invert in place, per block J: eight lanes of the last wave invert the
-//    diagonal block (one column each) while the other threads form
-//    T = X_{:,<J} R_{<J,J}, one (row, column) pair each, into LDS; after a
-//    barrier X_{<J,J} = -T X_JJ.
-// Dynamic LDS: the packed triangle plus 2 * 128 * kCholBlk doubles for T.
-constexpr int kCholBlk = 8;
-constexpr int kBlkThreads = 1024;
-__global__ __launch_bounds__(kBlkThreads) void chol_inv_blk_kernel(double* G, double* X, int n,
+// Register-resident variant of chol_inv_lds_kernel for n <= 128, same
+// contract, one workgroup of 1024 threads.  Factor and inverse come out of
+// one elimination on the augmented matrix [G | I]: step k scales row k by
+// 1/sqrt(pivot) and subtracts conj(R[k][i]) times it from every row i > k.
+// The elimination operator E is then lower triangular with E G = R, so
+// E = R^{-H}: the left block ends as R and the right block as R^{-H}.  Row i
+// of the two blocks shares one n-wide register row: columns j >= i hold the
+// left block's upper triangle and columns j < i the right block's strictly
+// lower part; the right block's diagonal entry of row k is 1/R[k][k].
+// Step k must leave columns k < j < i of row i alone (the right block is
+// still zero there); the update is applied to every column anyway and the
+// rubbish it leaves in those columns is discarded when column k' = j is
+// reached (row i's entry in column k is zeroed before step k adds to it), so
+// the inner update carries no per-lane predicate.
+// Rows go to the 16 wavefronts cyclically (row i -> wave i mod 16, a
+// wave-uniform index), lane l holds columns l and l + 64 (NS = 2 column
+// slots; NS = 1 for n <= 64), and the multiplier conj(R[k][i]) of row i is
+// read from the lane that holds column i of the published row.  The
+// wavefront that owns row k+1 updates it first, takes its pivot, scales it
+// and publishes it through a double-buffered LDS row at raised priority while
+// the others apply step k to their rows: one workgroup barrier per step.
+constexpr int kRegThreads = 1024;
+constexpr int kRegWaves = kRegThreads / 64;
+constexpr int kRegChunk = 32;   // rows of X per LDS transpose pass
+// 1/sqrt(d) for a positive normal d: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - d y^2) / 2 (quadratic convergence from its
+// ~2^-23 relative error), within an ulp or two of the correctly rounded value
+// at a quarter of the latency of sqrt followed by a division
+__device__ __forceinline__ double rsqrt_newton(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-d * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+template <int NS>
+__global__ __launch_bounds__(kRegThreads) void chol_inv_reg_kernel(double* G, double* X, int n,
                                                                    int64_t plane,
                                                                    const double* shift,
                                                                    int* flag, const int* stop,
                                                                    int* converged) {
+    constexpr int ROWS = NS * 64 / kRegWaves;   // rows per wavefront
     if (stop && *stop) return;
-    extern __shared__ double lds[];
-    const int T = n * (n + 1) / 2;
-    double* Pr = lds;
-    double* Pi = lds + T;
-    double* Tr = lds + 2 * T;            // [row < 128][kCholBlk]
-    double* Ti = Tr + 128 * kCholBlk;
-    __shared__ double red[kBlkThreads / 64];
-    __shared__ double xdr[kCholBlk * kCholBlk], xdi[kCholBlk * kCholBlk];
+    __shared__ double red[kRegWaves];
+    __shared__ double2 pub[2][64 * NS];
+    __shared__ double dinv[64 * NS];   // 1 / R[i][i]
+    // X staging: kRegChunk rows of X (columns of E), padded rows
+    __shared__ double2 stage[kRegChunk][64 * NS + 1];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double s = shift ? shift[0] : 0.0;
     if (!shift && chol_near_identity(G, X, n, plane, converged, red)) return;
-    chol_pack(G, n, plane, s, Pr, Pi);
+    double wr[ROWS][NS], wi[ROWS][NS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int i = wave + kRegWaves * r;
+#pragma unroll
+        for (int h = 0; h < NS; ++h) {
+            const int j = lane + 64 * h;
+            const bool in = i < n && j < n;
+            const double vr = in ? G[(int64_t)i * n + j] : 0.0;
+            const double vi = in ? G[(int64_t)i * n + j + plane] : 0.0;
+            const bool up = in && j >= i;
+            wr[r][h] = up ? vr + ((j == i) ? s : 0.0) : 0.0;
+            wi[r][h] = (up && j != i) ? vi : 0.0;
+        }
+    }
+    // step k on row i (slot r); column k sits in column slot KH
+#define FTD_CHOL_UPDATE(r, i, KH)                                               \
+    do {                                                                        \
+        const bool hi_ = (r) * kRegWaves >= 64;                                 \
+        const double mr_ = lane_read(hi_ ? bjr[NS - 1] : bjr[0], (i) & 63);     \
+        const double mi_ = -lane_read(hi_ ? bji[NS - 1] : bji[0], (i) & 63);    \
+        wr[r][KH] *= keep;                                                      \
+        wi[r][KH] *= keep;                                                      \
+        _Pragma("unroll") for (int h = 0; h < NS; ++h) {                        \
+            wr[r][h] = fma(mi_, bji[h], fma(-mr_, bjr[h], wr[r][h]));           \
+            wi[r][h] = fma(-mi_, bjr[h], fma(-mr_, bji[h], wi[r][h]));          \
+        }                                                                       \
+    } while (0)
+    // row i (slot r of this wavefront) is final: pivot, scale, publish
+#define FTD_CHOL_PUBLISH(r, i, b)                                               \
+    do {                                                                        \
+        const bool hi_ = (r) * kRegWaves >= 64;                                 \
+        const double d_ = lane_read(hi_ ? wr[r][NS - 1] : wr[r][0], (i) & 63);  \
+        double p_ = 1.0, inv_ = 1.0;                                            \
+        if (!(d_ > 0.0) || !isfinite(d_)) {                                     \
+            if (lane == 0) flag[0] = 1;                                         \
+        } else {                                                                \
+            inv_ = rsqrt_newton(d_);                                            \
+            p_ = d_ * inv_;                                                     \
+        }                                                                       \
+        if (lane == 0) dinv[i] = inv_;                                          \
+        _Pragma("unroll") for (int h = 0; h < NS; ++h) {                        \
+            const int j = lane + 64 * h;                                        \
+            if (j == (i)) {                                                     \
+                wr[r][h] = p_;                                                  \
+                wi[r][h] = 0.0;                                                 \
+            } else {                                                            \
+                wr[r][h] *= inv_;                                               \
+                wi[r][h] *= inv_;                                               \
+            }                                                                   \
+            if (j < n)                                                          \
+                pub[b][j] = make_double2(j == (i) ? inv_ : wr[r][h],            \
+                                         j == (i) ? 0.0 : wi[r][h]);            \
+        }                                                                       \
+    } while (0)
+    // one elimination step; KH is the column slot of column k
+#define FTD_CHOL_STEP(KH)                                                       \
+    do {                                                                        \
+        const double2* row = pub[k & 1];                                        \
+        _Pragma("unroll") for (int h = 0; h < NS; ++h) {                        \
+            const int j = lane + 64 * h;                                        \
+            const double2 v = (j < n) ? row[j] : make_double2(0.0, 0.0);        \
+            bjr[h] = v.x;                                                       \
+            bji[h] = v.y;                                                       \
+        }                                                                       \
+        const double keep = (lane == (k & 63)) ? 0.0 : 1.0;                     \
+        const int nx = k + 1;                                                   \
+        const bool piv = nx < n && wave == nx % kRegWaves;                      \
+        const int rs = nx / kRegWaves;                                          \
+        if (piv) {                                                              \
+            __builtin_amdgcn_s_setprio(2);                                      \
+            _Pragma("unroll") for (int r = 0; r < ROWS; ++r) {                  \
+                if (r == rs) {                                                  \
+                    FTD_CHOL_UPDATE(r, nx, KH);                                 \
+                    FTD_CHOL_PUBLISH(r, nx, nx & 1);                            \
+                }                                                               \
+            }                                                                   \
+            __builtin_amdgcn_s_setprio(0);                                      \
+        }                                                                       \
+        _Pragma("unroll") for (int r = 0; r < ROWS; ++r) {                      \
+            const int i = wave + kRegWaves * r;                                 \
+            if (i > k && i < n && !(piv && r == rs)) FTD_CHOL_UPDATE(r, i, KH); \
+        }                                                                       \
+        __syncthreads();                                                        \
+    } while (0)
+    double bjr[NS], bji[NS];
+    if (wave == 0) FTD_CHOL_PUBLISH(0, 0, 0);
     __syncthreads();
-
-    // ------------------------------------------------------------ factor
-    const int ty = tid >> 5, tx = tid & 31;   // 32 row groups x 32 columns
-    for (int kb = 0; kb < n; kb += kCholBlk) {
-        const int nb = min(kCholBlk, n - kb);
-        if (wave < 2) {
-            // waves 0 and 1 both factor the diagonal block (identical
-            // arithmetic), then each solves its half of the block row
-            const int r = lane >> 3, c = lane & 7;
-            const bool own = r < nb && c < nb && r <= c;
-            double dr = 0.0, di = 0.0;
-            if (own) {
-                dr = Pr[pk(kb + r, kb + c, n)];
-                di = (r == c) ? 0.0 : Pi[pk(kb + r, kb + c, n)];
-            }
-            for (int k = 0; k < nb; ++k) {
-                double p = __shfl(dr, k * 8 + k, 64);
-                if (!(p > 0.0) || !isfinite(p)) {
-                    if (lane == 0 && wave == 0) flag[0] = 1;
-                    p = 1.0;
-                } else {
-                    p = sqrt(p);
-                }
-                const double ip = 1.0 / p;
-                if (own && r == k) {
-                    if (c == k) {
-                        dr = p;
-                        di = 0.0;
-                    } else {
-                        dr *= ip;
-                        di *= ip;
-                    }
-                }
-                const double kr = __shfl(dr, k * 8 + r, 64), ki = __shfl(di, k * 8 + r, 64);
-                const double cr = __shfl(dr, k * 8 + c, 64), ci = __shfl(di, k * 8 + c, 64);
-                if (own && r > k) {
-                    // G[r][c] -= conj(R[k][r]) R[k][c]
-                    dr -= kr * cr + ki * ci;
-                    di -= kr * ci - ki * cr;
-                }
-            }
-            if (own && wave == 0) {
-                Pr[pk(kb + r, kb + c, n)] = dr;
-                Pi[pk(kb + r, kb + c, n)] = di;
-            }
-            // block row: R_KK^H x = g, forward substitution, one column per
-            // lane; the factor comes from this wave's own registers
-            const int j = kb + nb + lane + 64 * wave;
-            const bool ok = j < n;
-            const int jj = ok ? j : n - 1;   // in-range address for idle lanes
-            double xr[kCholBlk], xi[kCholBlk];
+    const int k64 = min(n, 64);
+    for (int k = 0; k < k64; ++k) FTD_CHOL_STEP(0);
+    for (int k = 64; k < n; ++k) FTD_CHOL_STEP(NS - 1);
+#undef FTD_CHOL_STEP
+#undef FTD_CHOL_UPDATE
+#undef FTD_CHOL_PUBLISH
+    // R into G (zeros below the diagonal)
 #pragma unroll
-            for (int k = 0; k < kCholBlk; ++k) {
-                xr[k] = 0.0;
-                xi[k] = 0.0;
-                if (k < nb) {
-                    const double dinv = 1.0 / __shfl(dr, k * 8 + k, 64);
-                    double sr = ok ? Pr[pk(kb + k, jj, n)] : 0.0;
-                    double si = ok ? Pi[pk(kb + k, jj, n)] : 0.0;
+    for (int r = 0; r < ROWS; ++r) {
+        const int i = wave + kRegWaves * r;
 #pragma unroll
-                    for (int l = 0; l < k; ++l) {
-                        // conj(R[l][k]) x_l
-                        const double ar = __shfl(dr, l * 8 + k, 64), ai = __shfl(di, l * 8 + k, 64);
-                        sr -= ar * xr[l] + ai * xi[l];
-                        si -= ar * xi[l] - ai * xr[l];
-                    }
-                    xr[k] = sr * dinv;
-                    xi[k] = si * dinv;
-                    if (ok) {
-                        Pr[pk(kb + k, jj, n)] = xr[k];
-                        Pi[pk(kb + k, jj, n)] = xi[k];
-                    }
+        for (int h = 0; h < NS; ++h) {
+            const int j = lane + 64 * h;
+            if (i < n && j < n) {
+                const bool up = j >= i;
+                G[(int64_t)i * n + j] = up ? wr[r][h] : 0.0;
+                G[(int64_t)i * n + j + plane] = up ? wi[r][h] : 0.0;
+            }
+        }
+    }
+    // X = R^{-1} = E^H: X[j][i] is conj(E[i][j]) for j < i, 1/R[i][i] for
+    // j = i and zero for j > i; transposed through LDS, kRegChunk rows of X
+    // (columns j of E) per pass, then written row by row
+    for (int c0 = 0; c0 < n; c0 += kRegChunk) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int i = wave + kRegWaves * r;
+#pragma unroll
+            for (int h = 0; h < NS; ++h) {
+                const int j = lane + 64 * h;
+                if (i < n && j >= c0 && j < c0 + kRegChunk && j < n) {
+                    const double xr = (j < i) ? wr[r][h] : (j == i ? dinv[i] : 0.0);
+                    const double xi = (j < i) ? -wi[r][h] : 0.0;
+                    stage[j - c0][i] = make_double2(xr, xi);
                 }
             }
         }
         __syncthreads();
-        // trailing update of rows and columns >= kb + nb
-        for (int i = kb + nb + ty; i < n; i += 32) {
-            double ar[kCholBlk], ai[kCholBlk];
-#pragma unroll
-            for (int k = 0; k < kCholBlk; ++k) {
-                ar[k] = k < nb ? Pr[pk(kb + k, i, n)] : 0.0;
-                ai[k] = k < nb ? -Pi[pk(kb + k, i, n)] : 0.0;
-            }
-            const int ri = pk(i, i, n);
-            for (int j = i + tx; j < n; j += 32) {
-                double sr = Pr[ri + (j - i)], si = Pi[ri + (j - i)];
-#pragma unroll
-                for (int k = 0; k < kCholBlk; ++k) {
-                    if (k < nb) {
-                        const double br = Pr[pk(kb + k, j, n)], bi = Pi[pk(kb + k, j, n)];
-                        sr -= ar[k] * br - ai[k] * bi;
-                        si -= ar[k] * bi + ai[k] * br;
-                    }
-                }
-                Pr[ri + (j - i)] = sr;
-                Pi[ri + (j - i)] = si;
-            }
+        const int rows = min(kRegChunk, n - c0);
+        for (int e = tid; e < rows * n; e += kRegThreads) {
+            const int jr = e / n, i = e - jr * n;
+            const double2 v = stage[jr][i];
+            X[(int64_t)(c0 + jr) * n + i] = v.x;
+            X[(int64_t)(c0 + jr) * n + i + plane] = v.y;
         }
         __syncthreads();
-    }
-    for (int e = tid; e < n * n; e += kBlkThreads) {
-        const int i = e / n, j = e - i * n;
-        G[e] = (j >= i) ? Pr[pk(i, j, n)] : 0.0;
-        G[e + plane] = (j >= i) ? Pi[pk(i, j, n)] : 0.0;
-    }
-    __syncthreads();
-
-    // ----------------------------------------------------------- inverse
-    const int cc = tid & 7, ig = tid >> 3;   // 128 rows x 8 columns
-    for (int jb = 0; jb < n; jb += kCholBlk) {
-        const int nb = min(kCholBlk, n - jb);
-        // the last wavefront has no T rows (8 * jb <= 960): it inverts the
-        // diagonal block while the others form T
-        if (wave == kBlkThreads / 64 - 1 && lane < nb) {
-            // column c of the diagonal block's inverse, back substitution
-            const int c = lane;
-            double xr[kCholBlk], xi[kCholBlk];
-#pragma unroll
-            for (int r = kCholBlk - 1; r >= 0; --r) {
-                xr[r] = 0.0;
-                xi[r] = 0.0;
-                if (r == c) {
-                    xr[r] = 1.0 / Pr[pk(jb + r, jb + r, n)];
-                } else if (r < c) {
-                    double sr = 0.0, si = 0.0;
-#pragma unroll
-                    for (int k = r + 1; k < kCholBlk; ++k) {
-                        if (k <= c) {
-                            const double rr = Pr[pk(jb + r, jb + k, n)], ri = Pi[pk(jb + r, jb + k, n)];
-                            sr += rr * xr[k] - ri * xi[k];
-                            si += rr * xi[k] + ri * xr[k];
-                        }
-                    }
-                    const double inv = 1.0 / Pr[pk(jb + r, jb + r, n)];
-                    xr[r] = -sr * inv;
-                    xi[r] = -si * inv;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < kCholBlk; ++r) {
-                xdr[r * kCholBlk + c] = xr[r];
-                xdi[r * kCholBlk + c] = xi[r];
-            }
-        }
-        // T[i][c] = sum_{i <= k < jb} X[i][k] R[k][jb + c], rows i < jb
-        for (int i = ig; i < jb; i += kBlkThreads / kCholBlk) {
-            if (cc < nb) {
-                double sr = 0.0, si = 0.0;
-                for (int k = i; k < jb; ++k) {
-                    const double xr_ = Pr[pk(i, k, n)], xi_ = Pi[pk(i, k, n)];
-                    const double rr = Pr[pk(k, jb + cc, n)], ri = Pi[pk(k, jb + cc, n)];
-                    sr += xr_ * rr - xi_ * ri;
-                    si += xr_ * ri + xi_ * rr;
-                }
-                Tr[i * kCholBlk + cc] = sr;
-                Ti[i * kCholBlk + cc] = si;
-            }
-        }
-        __syncthreads();   // diagonal inverse and T visible; column block J fully read
-        for (int i = ig; i < jb; i += kBlkThreads / kCholBlk) {
-            if (cc < nb) {
-                double ur = 0.0, ui = 0.0;
-#pragma unroll
-                for (int c = 0; c < kCholBlk; ++c) {
-                    if (c <= cc) {
-                        const double ar = Tr[i * kCholBlk + c], ai = Ti[i * kCholBlk + c];
-                        const double br = xdr[c * kCholBlk + cc], bi = xdi[c * kCholBlk + cc];
-                        ur += ar * br - ai * bi;
-                        ui += ar * bi + ai * br;
-                    }
-                }
-                Pr[pk(i, jb + cc, n)] = -ur;
-                Pi[pk(i, jb + cc, n)] = -ui;
-            }
-        }
-        if (tid < kCholBlk * kCholBlk) {
-            const int r = tid >> 3, c = tid & 7;
-            if (r <= c && c < nb) {
-                Pr[pk(jb + r, jb + c, n)] = xdr[r * kCholBlk + c];
-                Pi[pk(jb + r, jb + c, n)] = xdi[r * kCholBlk + c];
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < n * n; e += kBlkThreads) {
-        const int i = e / n, j = e - i * n;
-        X[e] = (j >= i) ? Pr[pk(i, j, n)] : 0.0;
-        X[e + plane] = (j >= i) ? Pi[pk(i, j, n)] : 0.0;
     }
 }
 
@@ -572,40 +541,37 @@ static GemmParams gp(int M, int N, int K) {
 
 // Shifted CholeskyQR3.  wide == false: M is m x n (row-major), M = Q R.
 // wide == true: M is n x m (row-major), M = L Q with L = R^H.
-// Factor-and-invert of the n x n Gram matrix: LDS kernel when its packed
-// triangle fits the per-workgroup LDS, else the global-memory kernels.
+// Factor-and-invert of the n x n Gram matrix: the register kernel up to
+// n = 128, the LDS kernel while the packed triangle fits the per-workgroup
+// LDS, else the global-memory kernels.
 static bool chol_lds_fits(Ctx* ctx, int64_t n) {
     int lim = 0;
     FTD_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
     return sizeof(double) * (size_t)(n * (n + 1)) + 64 <= (size_t)lim;
 }
-static bool blk_fits(Ctx* ctx, int64_t n) {
-    int lim = 0;
-    FTD_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-    // packed triangle, the T staging block and the kernel's static arrays
-    return sizeof(double) * (size_t)(n * (n + 1) + 2 * 128 * kCholBlk + 2 * kCholBlk * kCholBlk +
-                                     kBlkThreads / 64) <=
-           (size_t)lim;
-}
 static void chol_inv(Ctx* ctx, double* G, double* Xi, int64_t n, const double* shift, int* flag,
                      int* converged) {
     const int64_t nn = n * n;
+    if (n <= 0) return;
+    if (n <= 64) {
+        chol_inv_reg_kernel<1><<<1, kRegThreads, 0, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag,
+                                                                    ctx->kstop, converged);
+        FTD_HIP(hipGetLastError());
+        return;
+    }
+    if (n <= 128) {
+        chol_inv_reg_kernel<2><<<1, kRegThreads, 0, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag,
+                                                                    ctx->kstop, converged);
+        FTD_HIP(hipGetLastError());
+        return;
+    }
     const size_t bytes = sizeof(double) * (size_t)(n * (n + 1));
     bool lds = chol_lds_fits(ctx, n);
     if (lds && bytes > 48 * 1024)
         lds = hipFuncSetAttribute((const void*)chol_inv_lds_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
               hipSuccess;
-    const size_t bbytes = bytes + sizeof(double) * 2 * 128 * kCholBlk;
-    bool blk = lds && n >= 16 && n <= 128 && blk_fits(ctx, n);
-    if (blk && bbytes > 48 * 1024)
-        blk = hipFuncSetAttribute((const void*)chol_inv_blk_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bbytes) ==
-              hipSuccess;
-    if (blk) {
-        chol_inv_blk_kernel<<<1, kBlkThreads, bbytes, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag,
-                                                                      ctx->kstop, converged);
-    } else if (lds) {
+    if (lds) {
         chol_inv_lds_kernel<<<1, kCholThreads, bytes, ctx->stream>>>(G, Xi, (int)n, nn, shift, flag,
                                                                      ctx->kstop, converged);
     } else {

@@ -3,10 +3,10 @@ CholeskyQR in three passes) through the C ABI, against the definition of a QR
 (LQ) factorisation: Q has orthonormal columns (rows), the product reproduces
 M, the triangular factor has a real positive diagonal, and for well-
 conditioned M it equals LAPACK's factor in the same gauge.  Sizes cover the
-small-n Cholesky kernel (n < 16), the blocked one (16 <= n <= 128, including
-ragged last blocks), the column kernel (n = 140) and the global-memory path
-(n = 200); condition numbers up to 1e10, as the Schmidt spectra kept at a
-1e-10 cutoff produce."""
+register Cholesky kernel (n <= 128: one column per lane up to n = 64, two
+above, rows dealt unevenly over the wavefronts), the LDS kernel (n = 140) and
+the global-memory path (n = 200); condition numbers up to 1e10, as the
+Schmidt spectra kept at a 1e-10 cutoff produce."""
 import numpy as np
 import pytest
 
@@ -30,7 +30,8 @@ def positive_gauge(R):
     return R * ph.conj()[:, None]
 
 
-CASES = [(12, 5, 1.0), (40, 16, 1e4), (300, 17, 1e8), (500, 23, 1.0), (1000, 64, 1e10),
+CASES = [(700, 1, 1.0), (12, 5, 1.0), (40, 16, 1e4), (4000, 65, 1e8), (300, 17, 1e8),
+         (500, 23, 1.0), (1000, 64, 1e10),
          (2000, 100, 1e6), (12800, 128, 1e10), (3000, 127, 1e3), (1500, 140, 1e6),
          (2000, 200, 1e4)]
 
