@@ -191,7 +191,8 @@ struct KrylovDev {
 };
 void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
                     int exhausted);
-void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane);
+void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane,
+                    float* out32 = nullptr);
 void k_set_alpha(Ctx* ctx, KrylovDev kd, int k);
 void k_krylov_reset(Ctx* ctx, KrylovDev kd);
 
@@ -290,6 +291,19 @@ struct Ctx {
     DBuf ws_A32;
     double* scal = nullptr;       // device scalars (Krylov state etc.)
     int* iscal = nullptr;
+    // Float copies of Krylov vectors: every workspace reallocation bumps
+    // ws_gen; load_slot records where it put the compute-precision copy of
+    // its input (last32_*), and a Lanczos normalisation that already wrote
+    // the next vector's copy there marks it (pre32_*) so the next load of
+    // that vector is skipped.
+    uint64_t ws_gen = 0;
+    const double* last32_x = nullptr;
+    void* last32_dst = nullptr;
+    int64_t last32_n = 0;
+    uint64_t last32_gen = 0;
+    const double* pre32_x = nullptr;
+    const void* pre32_dst = nullptr;
+    uint64_t pre32_gen = 0;
     int* h_pinned_i = nullptr;    // host pinned readback
     double* h_pinned_d = nullptr;
     KrylovDev kd{};

@@ -48,6 +48,7 @@ void DBuf::ensure(Ctx* ctx, size_t need) {
     size_t want = need + need / 4 + 256;
     p = dev_alloc(ctx, want);
     bytes = want;
+    ctx->ws_gen++;
 }
 void DBuf::release(Ctx* ctx) {
     dev_free(ctx, p);
@@ -326,10 +327,19 @@ static void boundary_env(Ctx* ctx, EnvView e, Prec prec) {
 
 // compute-precision copy of a site tensor into slot `slot` of ws_T
 static void load_slot(Ctx* ctx, Prec prec, const double* x, int64_t n, void* Tbase, int slot) {
-    if (prec == Prec::F64)
+    if (prec == Prec::F64) {
         k_copy_f64(ctx, x, static_cast<double*>(Tbase) + (int64_t)slot * 2 * n, 2 * n);
-    else
-        k_convert_f64_f32(ctx, x, static_cast<float*>(Tbase) + (int64_t)slot * 2 * n, 2 * n);
+        ctx->last32_x = nullptr;
+        return;
+    }
+    float* dst = static_cast<float*>(Tbase) + (int64_t)slot * 2 * n;
+    const bool ready = x == ctx->pre32_x && dst == ctx->pre32_dst && ctx->pre32_gen == ctx->ws_gen;
+    ctx->pre32_x = nullptr;
+    if (!ready) k_convert_f64_f32(ctx, x, dst, 2 * n);
+    ctx->last32_x = x;
+    ctx->last32_dst = dst;
+    ctx->last32_n = n;
+    ctx->last32_gen = ctx->ws_gen;
 }
 
 static const void* ops_of(const MpoSite& W, Prec prec) {
@@ -663,15 +673,16 @@ static void env_right_update(Ctx* ctx, Prec prec, const MpoSite& W, int Da, int 
 }
 
 // ================================================================ Krylov
-// x <- exp(z Op) x by Lanczos with full (twice-applied classical
-// Gram-Schmidt) reorthogonalisation in float64.
-// exp(z H) x for the Hermitian operator `op`, by Lanczos with full
-// reorthogonalisation (classical Gram-Schmidt applied twice) and the device
-// tridiagonal exponential.  Iterations are enqueued without waiting; every
-// kernel of an iteration returns at once after the device has raised the halt
-// flag, so the host reads the flags only from the expected vector count on
-// (hint: the count of the previous call at the same site or bond).  Timing events and
-// matvec counts of iterations that ran as no-ops are discarded.
+// x <- exp(z H) x for the Hermitian operator `op`, by Lanczos with full
+// reorthogonalisation in float64 (classical Gram-Schmidt applied twice) and
+// the device tridiagonal exponential.  Iterations are enqueued without
+// waiting; every kernel of an iteration returns at once after the device has
+// raised the halt flag, so the host reads the flags only from the expected
+// vector count on (hint: the count of the previous call at the same site or
+// bond); the vector count itself does not depend on the hint.  Timing
+// events and matvec counts of iterations that ran as no-ops are discarded.
+// In the reduced precisions the normalisation of each new vector also writes
+// the float copy the next matvec reads.
 static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*)>& op, double* x,
                        int64_t n, cplx z, double tol, int mmax, int& last) {
     FTD_CHECK(mmax >= 1 && mmax < kMaxKrylov, FTD_EINVAL, "Krylov mmax out of range");
@@ -697,6 +708,7 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
             fl_mark[k] = ctx->stats.all_flops;
             double* vk = V + (int64_t)k * vs;
             double* w = V + (int64_t)(k + 1) * vs;
+            ctx->last32_x = nullptr;
             op(vk, w);
             // classical Gram-Schmidt twice; alpha_k = <v_k, w> of the first pass
             k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h, kd.alpha + k);
@@ -707,7 +719,19 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
             k_multiaxpy_nrm2(ctx, V, vs, k + 1, kd.h, w, n, n, kd.nrm);
             const int exhausted = (k + 1 == n) ? 1 : 0;
             k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted);
-            k_lanczos_post(ctx, kd, k + 1, w, n, n);
+            // the normalised w is the next matvec's input: when the matvec just
+            // loaded its input as a float copy, the normalisation writes the
+            // next one in the same place
+            float* w32 = nullptr;
+            if (ctx->last32_x == vk && ctx->last32_n == n && ctx->last32_gen == ctx->ws_gen &&
+                k + 1 < kmax)
+                w32 = static_cast<float*>(ctx->last32_dst);
+            k_lanczos_post(ctx, kd, k + 1, w, n, n, w32);
+            if (w32) {
+                ctx->pre32_x = w;
+                ctx->pre32_dst = w32;
+                ctx->pre32_gen = ctx->ws_gen;
+            }
             if (k + 1 < hint && k + 1 < kmax) continue;
             FTD_HIP(hipMemcpyAsync(ctx->h_pinned_i, kd.flag, 4 * sizeof(int),
                                    hipMemcpyDeviceToHost, ctx->stream));
@@ -719,9 +743,11 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
         }
     } catch (...) {
         ctx->kstop = nullptr;
+        ctx->pre32_x = ctx->last32_x = nullptr;
         throw;
     }
     ctx->kstop = nullptr;
+    ctx->pre32_x = ctx->last32_x = nullptr;
     if (!done) throw Error{FTD_ENOCONV, "Krylov exponential did not converge within mmax vectors"};
     const int conv = ctx->h_pinned_i[0], failed = ctx->h_pinned_i[2], m = ctx->h_pinned_i[1];
     FTD_CHECK(!failed || conv, FTD_ENOCONV,

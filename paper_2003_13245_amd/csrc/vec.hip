@@ -654,14 +654,14 @@ __global__ __launch_bounds__(64) void tridiag_expm_kernel(KrylovDev kd, int n, d
             }
             const double dl = lane_get(dj, l), el = lane_get(ej, l);
             double g = (lane_get(dj, l + 1) - dl) / (2.0 * el);
-            double r = hypot(g, 1.0);
+            double r = sqrt(fma(g, g, 1.0));
             g = lane_get(dj, m) - dl + el / (g + copysign(r, g));
             double s = 1.0, c = 1.0, p = 0.0;
             bool early = false;
             for (int i = m - 1; i >= l; --i) {
                 const double ei = lane_get(ej, i);
                 const double f = s * ei, b = c * ei;
-                r = hypot(f, g);
+                r = sqrt(fma(f, f, g * g));
                 if (j == i + 1) ej = r;
                 if (r == 0.0) {
                     const double v = lane_get(dj, i + 1) - p;
@@ -691,16 +691,21 @@ __global__ __launch_bounds__(64) void tridiag_expm_kernel(KrylovDev kd, int n, d
         }
     }
     __syncthreads();
-    // u_j = sum_i Z[j][i] exp(z lambda_i) Z[0][i]
+    // u_j = sum_i Z[j][i] exp(z lambda_i) Z[0][i]; the factors
+    // exp(z lambda_i) Z[0][i] are formed one eigenvalue per lane
+    double cr = 0.0, ci = 0.0;
+    if (j < n) {
+        const double mag = exp(zr * dj);
+        double sn, cs;
+        sincos(zi * dj, &sn, &cs);
+        cr = mag * cs * Z[0][j];
+        ci = mag * sn * Z[0][j];
+    }
     double ur = 0.0, ui = 0.0;
     for (int i = 0; i < n; ++i) {
-        const double lam = lane_get(dj, i);
-        const double mag = exp(zr * lam);
-        const double er = mag * cos(zi * lam), ei = mag * sin(zi * lam);
-        const double w0 = Z[0][i];
         const double zz = (j < n) ? Z[j][i] : 0.0;
-        ur += zz * er * w0;
-        ui += zz * ei * w0;
+        ur += zz * lane_get(cr, i);
+        ui += zz * lane_get(ci, i);
     }
     double nn = (j < n) ? ur * ur + ui * ui : 0.0;
     for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
@@ -723,15 +728,22 @@ __global__ __launch_bounds__(64) void tridiag_expm_kernel(KrylovDev kd, int n, d
     }
 }
 
-// w /= beta_{n-1} unless converged
-__global__ void lanczos_post_kernel(KrylovDev kd, int n, double* w, int64_t len, int64_t plane) {
+// w /= beta_{n-1} unless converged (the next Lanczos vector); with out32,
+// also its float copy
+__global__ void lanczos_post_kernel(KrylovDev kd, int n, double* w, int64_t len, int64_t plane,
+                                    float* out32) {
     if (kd.flag[3]) return;
     const double b = kd.beta[n - 1];
     const double f = 1.0 / b;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
          i += (int64_t)gridDim.x * blockDim.x) {
-        w[i] *= f;
-        w[i + plane] *= f;
+        const double a = w[i] * f, c = w[i + plane] * f;
+        w[i] = a;
+        w[i + plane] = c;
+        if (out32) {
+            out32[i] = (float)a;
+            out32[i + plane] = (float)c;
+        }
     }
 }
 __global__ void set_alpha_kernel(KrylovDev kd, int k) {
@@ -754,8 +766,9 @@ void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double 
     tridiag_expm_kernel<<<1, 64, 0, ctx->stream>>>(kd, k, zr, zi, tol, exhausted, kMaxKrylov);
     FTD_HIP(hipGetLastError());
 }
-void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane) {
-    lanczos_post_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(kd, k, w, n, plane);
+void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane,
+                    float* out32) {
+    lanczos_post_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(kd, k, w, n, plane, out32);
     FTD_HIP(hipGetLastError());
 }
 void k_set_alpha(Ctx* ctx, KrylovDev kd, int k) {
