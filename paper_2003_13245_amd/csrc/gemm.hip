@@ -518,9 +518,12 @@ static void launch(Ctx* ctx, const void* A, const void* B, void* C, const GemmPa
 }
 
 // Number of k-splits of a launch: when the output tiles alone give fewer
-// than 512 workgroups and there is enough depth, the summed k range is split
-// so that about 1024 workgroups run, each over at least 4 k-tiles (at most
-// 64 splits).  Returns 0 for a launch with nothing to compute.
+// workgroups than there are compute units and there is enough depth, the
+// summed k range is split so that about 1024 workgroups run, each over at
+// least 4 k-tiles (at most 64 splits); a grid that already covers every
+// compute unit is not split (the partial planes and their reduction would
+// cost more than the imbalance of the last round of workgroups).  Returns 0
+// for a launch with nothing to compute.
 static int split_count(const GemmParams& p) {
     int nterms = 0;
     for (int i = 0; i < p.nprob; ++i) nterms = std::max(nterms, p.prob[i].t1 - p.prob[i].t0);
@@ -529,7 +532,7 @@ static int split_count(const GemmParams& p) {
     const int ktiles = nterms * ((p.K + GBK - 1) / GBK);
     const int blocks = tm * tn * p.nprob;
     int ks = 1;
-    if (blocks < 512 && ktiles >= 8) {
+    if (blocks < 256 && ktiles >= 8) {
         ks = (1024 + blocks - 1) / blocks;
         ks = std::min(ks, ktiles / 4);
         ks = std::min(ks, 64);

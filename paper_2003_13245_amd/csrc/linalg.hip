@@ -614,7 +614,9 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
     int* converged = ctx->iscal + 10;
     const bool lds_path = chol_lds_fits(ctx, n);
     set_int_kernel<<<1, 1, 0, ctx->stream>>>(converged, 0);
-    eye_kernel<<<grid1(nn), 256, 0, ctx->stream>>>(Rout, (int)n, nn);
+    // the passes alternate between M and Q2; after three the result is in Q2
+    double* in = M;
+    double* out = Q2;
     for (int pass = 0; pass < 3; ++pass) {
         // the third pass is predicated on the second pass's verdict
         const int* saved_stop = ctx->kstop;
@@ -631,35 +633,41 @@ static void chol_qr_impl(Ctx* ctx, double* M, int64_t m, int64_t n, double* Rout
             p.sBk = 1; p.sBn = m; p.planeB = mn; p.conjB = 1; p.b_kcontig = 1;
         }
         p.sCm = n; p.sCn = 1; p.planeC = nn;
-        gemm(ctx, Prec::F64, true, M, M, G, p, TAG_NONE);
+        gemm(ctx, Prec::F64, true, in, in, G, p, TAG_NONE);
         if (pass == 0) {
             const double c = 11.0 * ((double)m * n + (double)n * (n + 1));
             shift_kernel<<<1, 256, 0, ctx->stream>>>(G, (int)n, c, shift);
         }
         chol_inv(ctx, G, Xi, n, pass == 0 ? shift : nullptr, flag,
                  pass == 1 && lds_path ? converged : nullptr);
-        // M <- M Xi (tall) or M <- Xi^H M (wide)
+        // out <- in Xi (tall) or out <- Xi^H in (wide)
         GemmParams q = gp(wide ? (int)n : (int)m, wide ? (int)m : (int)n, (int)n);
         if (!wide) {
             q.sAm = n; q.sAk = 1; q.planeA = mn; q.a_kcontig = 1;
             q.sBk = n; q.sBn = 1; q.planeB = nn; q.b_kcontig = 0;
             q.sCm = n; q.sCn = 1; q.planeC = mn;
-            gemm(ctx, Prec::F64, true, M, Xi, Q2, q, TAG_NONE);
+            gemm(ctx, Prec::F64, true, in, Xi, out, q, TAG_NONE);
         } else {
-            // Q2[i][k] = sum_j conj(Xi[j][i]) M[j][k]
+            // out[i][k] = sum_j conj(Xi[j][i]) in[j][k]
             q.sAm = 1; q.sAk = n; q.planeA = nn; q.conjA = 1; q.a_kcontig = 0;
             q.sBk = m; q.sBn = 1; q.planeB = mn; q.b_kcontig = 0;
             q.sCm = m; q.sCn = 1; q.planeC = mn;
-            gemm(ctx, Prec::F64, true, Xi, M, Q2, q, TAG_NONE);
+            gemm(ctx, Prec::F64, true, Xi, in, out, q, TAG_NONE);
         }
-        k_copy_f64(ctx, Q2, M, 2 * mn);
-        // R <- U_pass R
-        GemmParams r = gp((int)n, (int)n, (int)n);
-        r.sAm = n; r.sAk = 1; r.planeA = nn; r.a_kcontig = 1;
-        r.sBk = n; r.sBn = 1; r.planeB = nn; r.b_kcontig = 0;
-        r.sCm = n; r.sCn = 1; r.planeC = nn;
-        gemm(ctx, Prec::F64, true, G, Rout, Rt, r, TAG_NONE);
-        k_copy_f64(ctx, Rt, Rout, 2 * nn);
+        // R <- U_pass R (the first pass's factor is R itself)
+        if (pass == 0) {
+            k_copy_f64(ctx, G, Rout, 2 * nn);
+        } else {
+            GemmParams r = gp((int)n, (int)n, (int)n);
+            r.sAm = n; r.sAk = 1; r.planeA = nn; r.a_kcontig = 1;
+            r.sBk = n; r.sBn = 1; r.planeB = nn; r.b_kcontig = 0;
+            r.sCm = n; r.sCn = 1; r.planeC = nn;
+            gemm(ctx, Prec::F64, true, G, Rout, Rt, r, TAG_NONE);
+            k_copy_f64(ctx, Rt, Rout, 2 * nn);
+        }
+        // a skipped third pass leaves the second pass's result in M
+        if (pass == 2) k_copy_f64(ctx, out, M, 2 * mn);
+        std::swap(in, out);
         ctx->kstop = saved_stop;
     }
     FTD_HIP(hipGetLastError());
