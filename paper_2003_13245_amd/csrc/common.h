@@ -151,9 +151,10 @@ void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out);
 // h[j] = <V_j, w>, j < k; V_j at V + j*vstride
 void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double* w, int64_t n,
                 int64_t plane, double* h, double* alpha = nullptr);
-// w -= sum_j V_j h[j] and out[0] = |w|^2 in one pass
-void k_multiaxpy_nrm2(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
-                      double* w, int64_t n, int64_t plane, double* out);
+// w -= sum_j V_j h[j] in one pass, with |w|^2 left as block partials in ctx->ws_red;
+// returns their count
+int k_multiaxpy_nrm2_part(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
+                          double* w, int64_t n, int64_t plane);
 // w -= sum_j V_j h[j], then h[j] = <V_j, w> of the updated w, in one pass over
 // V and w; false (nothing done) when k or n is outside its range (k <= 16,
 // long vectors), so that the caller falls back to k_multiaxpy + k_multidot
@@ -189,8 +190,9 @@ struct KrylovDev {
     double* nrm;     // [4]
     int* flag;       // [4]: converged, k, failed, halt (converged or failed)
 };
+// the squared norm of the new residual is given as `nb` block partials
 void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
-                    int exhausted);
+                    int exhausted, const double* nrm_part, int nb);
 void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane,
                     float* out32 = nullptr);
 void k_set_alpha(Ctx* ctx, KrylovDev kd, int k);

@@ -716,9 +716,10 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
                 k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
                 k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
             }
-            k_multiaxpy_nrm2(ctx, V, vs, k + 1, kd.h, w, n, n, kd.nrm);
+            const int nb = k_multiaxpy_nrm2_part(ctx, V, vs, k + 1, kd.h, w, n, n);
             const int exhausted = (k + 1 == n) ? 1 : 0;
-            k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted);
+            k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted,
+                           ctx->ws_red.as<double>(), nb);
             // the normalised w is the next matvec's input: when the matvec just
             // loaded its input as a float copy, the normalisation writes the
             // next one in the same place

@@ -355,15 +355,15 @@ __global__ void multiaxpy_nrm_partial(const double* __restrict__ V, int64_t vstr
     s = block_sum(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
-void k_multiaxpy_nrm2(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
-                      double* w, int64_t n, int64_t plane, double* out) {
+int k_multiaxpy_nrm2_part(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
+                          double* w, int64_t n, int64_t plane) {
     const int nb = red_blocks(n);
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
     multiaxpy_nrm_partial<<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
                                                       ctx->kstop);
-    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 1, out, ctx->kstop);
     FTD_HIP(hipGetLastError());
+    return nb;
 }
 
 __global__ void multiaxpy_kernel(const double* __restrict__ V, int64_t vstride, int k,
@@ -628,13 +628,20 @@ __device__ __forceinline__ double lane_get(double v, int i) {
     return __hiloint2double(hi, lo);
 }
 
+// The squared norm of the new Lanczos residual arrives as `nb` block
+// partials (summed here in a fixed order, and stored to kd.nrm[0]).
 __global__ __launch_bounds__(64) void tridiag_expm_kernel(KrylovDev kd, int n, double zr,
                                                           double zi, double tol, int exhausted,
-                                                          int mmax) {
+                                                          int mmax, const double* nrm_part,
+                                                          int nb) {
     __shared__ double Z[kMaxKrylov][kMaxKrylov + 1];
     if (kd.flag[3]) return;   // an earlier iteration converged or failed
     const int j = threadIdx.x;
-    const double bnew = sqrt(fmax(kd.nrm[0], 0.0));
+    double nsq = 0.0;
+    for (int b = j; b < nb; b += 64) nsq += nrm_part[b];
+    for (int o = 32; o > 0; o >>= 1) nsq += __shfl_xor(nsq, o, 64);
+    if (j == 0) kd.nrm[0] = nsq;
+    const double bnew = sqrt(fmax(nsq, 0.0));
     double dj = (j < n) ? kd.alpha[j] : 0.0;
     double ej = (j < n - 1) ? kd.beta[j] : 0.0;
     for (int i = 0; i < n; ++i) Z[j][i] = (i == j) ? 1.0 : 0.0;
@@ -762,8 +769,9 @@ void k_krylov_reset(Ctx* ctx, KrylovDev kd) {
 }
 
 void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
-                    int exhausted) {
-    tridiag_expm_kernel<<<1, 64, 0, ctx->stream>>>(kd, k, zr, zi, tol, exhausted, kMaxKrylov);
+                    int exhausted, const double* nrm_part, int nb) {
+    tridiag_expm_kernel<<<1, 64, 0, ctx->stream>>>(kd, k, zr, zi, tol, exhausted, kMaxKrylov,
+                                                   nrm_part, nb);
     FTD_HIP(hipGetLastError());
 }
 void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane,
