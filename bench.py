@@ -8,9 +8,9 @@ bond dimension 128, T = 300 K), synthetic seeded parameters.
 A step is one step of the C(t) loop: one second-order one-site TDVP step of
 Psi_beta and one of j Psi_beta (run concurrently on two streams), and the
 overlap <Psi|j|Phi>.  The inputs (Psi_beta from the imaginary-time
-preparation, whose one-site steps expand the bonds up to D, and j Psi_beta
-compressed to D) are prepared before the timed region and stay resident in
-HBM.  The headline value is the mixed-precision path (complex64 contractions
+preparation in float64, whose one-site steps expand the bonds up to D, and
+j Psi_beta compressed to D) are prepared before the timed region and stay
+resident in HBM.  The headline value is the mixed-precision path (complex64 contractions
 on MFMA, float64 Krylov/QR/norms).  From the same inputs the first
 --compare-steps steps are then run in float64 (Krylov tolerance 1e-14), the
 reference for the C(t) and window-mobility errors, and with the BF16x3
@@ -184,9 +184,11 @@ def run_steps(api, ctx, H, J, psi0, phi0, steps, dt, tol, mmax, timing, roctx=No
         roctx.resume()
     b0 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         api.tdvp_pair(ctx, H, psi, phi, dt_real=dt, tol=tol, mmax=mmax)
         C.append(api.overlap(ctx, psi, J, phi))
+        if steps >= 20 and (i + 1) % 10 == 0:
+            log(f"[bench] step {i + 1}/{steps}")
     ctx.synchronize()
     t1 = time.perf_counter()
     b1 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
@@ -348,11 +350,12 @@ def main():
     mmax = r.krylov_mmax
 
     log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D}, "
-        f"{wl.precision} contractions, expansion {r.expand_tol:g})")
+        f"{r.prep_precision} contractions, Krylov tol {r.prep_krylov_tol:g}, "
+        f"expansion {r.expand_tol:g})")
     t0 = time.perf_counter()
     psi_beta, logz = api.thermal_prep(ctx, H, r.beta, r.n_imag, r.n_grow, r.D, cutoff=r.cutoff,
-                                      precision=wl.precision, tol=tol, mmax=mmax,
-                                      expand_tol=r.expand_tol)
+                                      precision=r.prep_precision, tol=r.prep_krylov_tol,
+                                      mmax=mmax, expand_tol=r.expand_tol)
     t_prep = time.perf_counter() - t0
     bonds = psi_beta.info()["bond_dims"]
     log(f"[bench] prep {t_prep:.1f} s, ln Z = {logz:.6f}, bonds max {max(bonds)} "
@@ -363,8 +366,10 @@ def main():
     pbonds = phi0.info()["bond_dims"]
     log(f"[bench] j|Psi> compressed in {t_j:.1f} s, bonds max {max(pbonds)} "
         f"mean {sum(pbonds) / len(pbonds):.1f}")
-    psi0 = psi_beta
-    c0 = api.overlap(ctx, psi0, J, phi0)
+    c0 = api.overlap(ctx, psi_beta, J, phi0)
+    # the timed steps run in the workload's precision from the float64 inputs
+    psi0 = _as(api, ctx, psi_beta, wl.precision)
+    phi0 = _as(api, ctx, phi0, wl.precision)
 
     # warmup (untimed), then the timed mixed-precision steps
     if args.warmup:
@@ -399,6 +404,7 @@ def main():
                    "bond_modes": m.n_nl, "levels": m.levels_loc, "D": r.D,
                    "T_K": r.T_K, "dt_fs": r.dt_fs, "krylov_tol": tol, "n_imag": r.n_imag,
                    "n_grow": r.n_grow, "expand_tol": r.expand_tol,
+                   "prep_precision": r.prep_precision, "prep_krylov_tol": r.prep_krylov_tol,
                    "psi_bond_max": max(bonds),
                    "psi_bond_mean": round(sum(bonds) / len(bonds), 1),
                    "phi_bond_max": max(pbonds), "phi_bond_mean": round(sum(pbonds) / len(pbonds), 1)},
@@ -406,7 +412,7 @@ def main():
         "whole_step_tflops": st["all_flops"] / el_mix / 1e12,
         "matvecs_per_step": st["matvecs"] / args.steps,
         "krylov_mean": st["krylov_vectors"] / max(st["expm_calls"], 1),
-        "prep_s": t_prep, "jcompress_s": t_j,
+        "prep_s": t_prep, "jcompress_s": t_j, "ln_Z": logz,
     }
     dom = st["dom_kind"]
     dom_avg_ms = st["dom_ms"] / max(st["dom_launches"], 1)
