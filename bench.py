@@ -78,48 +78,108 @@ def gemm_source_sha256():
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def _traffic_path(workload_name):
+    return os.path.join(HERE, "profiles", f"traffic_{workload_name}.json")
+
+
 def measured_traffic(kernel, workload_name):
     """HBM bytes per launch of `kernel` from the committed counter record
     (two rocprofv3 --pmc passes, FETCH_SIZE then WRITE_SIZE, calibrated by a
-    copy of known size), or None when there is none for this kernel and
-    workload or the kernel source changed since it was taken."""
-    path = os.path.join(HERE, "profiles", f"traffic_{workload_name}.json")
+    copy of known size; written by --traffic), or None when the record has no
+    entry for this kernel and workload or the GEMM source changed since the
+    counters were taken."""
+    path = _traffic_path(workload_name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel") != kernel or rec.get("gemm_source_sha256") != gemm_source_sha256():
+    if rec.get("workload") != workload_name or rec.get("gemm_source_sha256") != gemm_source_sha256():
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    ent = rec.get("kernels", {}).get(kernel)
+    return None if ent is None else float(ent["traffic_bytes_per_launch"])
+
+
+def _windows(log_path):
+    """Timed-steps window (t0, t1) and calibration-copy window (t0, t1, bytes),
+    boot-clock ns, as printed to `log_path` by a run of this script."""
+    import re
+    windows = {}
+    with open(log_path) as f:
+        for line in f:
+            m = re.search(r"timed region boottime_ns (\d+) (\d+)", line)
+            if m and "timed steps" not in windows:
+                windows["timed steps"] = (int(m.group(1)), int(m.group(2)))
+            m = re.search(r"calibration copy of (\d+) bytes boottime_ns (\d+) (\d+)", line)
+            if m and "calibration copy" not in windows:
+                windows["calibration copy"] = (int(m.group(2)), int(m.group(3)), int(m.group(1)))
+    return windows
+
+
+def _rows_in(csv_path, windows):
+    import csv
+    sel = {k: [] for k in windows}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            st = int(row["Start_Timestamp"])
+            for k, w in windows.items():
+                if w[0] <= st <= w[1]:
+                    sel[k].append(row)
+    return sel
 
 
 def summarize(kind, csv_path, log_path):
     """Summary of rocprofv3 CSV rows (kernel trace or counter collection)
     whose dispatch started inside the first timed window this script printed
     to `log_path` ("[bench] timed region boottime_ns t0 t1")."""
-    import collections
-    import csv
-    import re
-    windows = {}
-    with open(log_path) as f:
-        for line in f:
-            for label, pat in (("timed steps", r"timed region boottime_ns (\d+) (\d+)"),
-                               ("calibration copy",
-                                r"calibration copy of \d+ bytes boottime_ns (\d+) (\d+)")):
-                m = re.search(pat, line)
-                if m and label not in windows:
-                    windows[label] = (int(m.group(1)), int(m.group(2)))
+    windows = _windows(log_path)
     if "timed steps" not in windows:
         raise SystemExit("no timed window in the log")
-    sel = {k: [] for k in windows}
-    with open(csv_path) as f:
-        for row in csv.DictReader(f):
-            st = int(row["Start_Timestamp"])
-            for k, (a, b) in windows.items():
-                if a <= st <= b:
-                    sel[k].append(row)
+    sel = _rows_in(csv_path, windows)
     for label in windows:
-        summarize_rows(kind, label, windows[label], sel[label])
+        summarize_rows(kind, label, windows[label][:2], sel[label])
+
+
+def traffic_record(fetch_csv, fetch_log, write_csv, write_log, workload_name, commands):
+    """HBM traffic per launch of every GEMM instance in the timed steps, from
+    a FETCH_SIZE pass and a WRITE_SIZE pass (KiB per dispatch, counter
+    collection CSVs with their logs), each scaled by what the same counter
+    reads for the calibration copy of that run (a device copy of known size,
+    which reads and writes its size once)."""
+    import collections
+    out = {"workload": workload_name, "gemm_source_sha256": gemm_source_sha256(),
+           "commands": commands, "kernels": {}}
+    per = collections.defaultdict(dict)
+    for tag, csv_path, log_path, counter in (("fetch", fetch_csv, fetch_log, "FETCH_SIZE"),
+                                             ("write", write_csv, write_log, "WRITE_SIZE")):
+        windows = _windows(log_path)
+        if "timed steps" not in windows or "calibration copy" not in windows:
+            raise SystemExit(f"{log_path}: timed or calibration window missing")
+        sel = _rows_in(csv_path, windows)
+        copy_kib = sum(float(r["Counter_Value"]) for r in sel["calibration copy"]
+                       if r["Counter_Name"] == counter)
+        copy_bytes = windows["calibration copy"][2]
+        factor = copy_bytes / 1024.0 / copy_kib
+        out["calibration_copy_bytes"] = copy_bytes
+        out[f"{tag}_size_kib_for_copy"] = copy_kib
+        out[f"{tag}_factor"] = factor
+        kib = collections.defaultdict(float)
+        disp = collections.defaultdict(set)
+        for r in sel["timed steps"]:
+            if r["Counter_Name"] != counter or "gemm" not in r["Kernel_Name"]:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+            kib[name] += float(r["Counter_Value"])
+            disp[name].add(r.get("Dispatch_Id") or len(disp[name]))
+        for name in kib:
+            n = len(disp[name])
+            per[name][f"{tag}_size_kib_in_window"] = kib[name]
+            per[name][f"{tag}_dispatches_in_window"] = n
+            per[name][f"{tag}_bytes_per_launch"] = kib[name] * 1024.0 * factor / n
+    for name, e in per.items():
+        if "fetch_bytes_per_launch" in e and "write_bytes_per_launch" in e:
+            e["traffic_bytes_per_launch"] = e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+            out["kernels"][name] = e
+    return out
 
 
 def summarize_rows(kind, label, window, rows):
@@ -214,16 +274,11 @@ def blas_info():
     return os.cpu_count() or 1, "?"
 
 
-def cpu_baseline(wl, states, krylov_mean, rep_s=0.25):
-    """The oracle's time for one pair-step of this workload, assembled from
-    the oracle's own kernels timed on this host at every distinct site shape
-    of the two states as they enter the timed steps.  One state-step visits
-    every site twice (left-to-right, right-to-left sweep); a visit is
-    krylov_mean H_eff matvecs (the GPU run's mean Krylov vectors per
-    exponential), one gauge QR, one environment update and krylov_mean K_eff
-    matvecs on the bond; a pair-step is both states plus one overlap (one
-    transfer step per site).  Each distinct shape is timed once per kernel
-    (repeated up to rep_s), not extrapolated from one shape."""
+def oracle_kernel_times(wl, states, rep_s=0.25):
+    """The oracle's H_eff, gauge QR, environment-update and K_eff times on
+    this host at every distinct site shape of the two states, each timed once
+    (repeated up to rep_s); returns ({(Dl, Dr, W shape): times}, seconds of
+    CPU work spent)."""
     from oracle import mpo as OM
     from oracle import tdvp as T
     Hw = OM.hamiltonian_mpo(wl.model)
@@ -240,7 +295,7 @@ def cpu_baseline(wl, states, krylov_mean, rep_s=0.25):
                 return el / n
 
     cache = {}
-    t_step, n_shapes, t_sample = 0.0, 0, time.perf_counter()
+    t_sample = time.perf_counter()
     for bonds in states:
         L = len(Hw)
         for i in range(L):
@@ -249,23 +304,50 @@ def cpu_baseline(wl, states, krylov_mean, rep_s=0.25):
             a = 1 if i == 0 else bonds[i - 1]
             b = 1 if i == L - 1 else bonds[i]
             key = (a, b, W.shape)
-            if key not in cache:
-                Le, Re, A = cz(W.shape[0], a, a), cz(W.shape[1], b, b), cz(a, d, d, b)
-                C = cz(b, b)
-                t_h = timed(lambda: T.heff_apply(Le, W, Re, A))
-                t_q = timed(lambda: T.qr_pos(A.reshape(a * d * d, b)))
-                t_e = timed(lambda: T.left_env(Le, A, W, A))
-                t_k = timed(lambda: T.keff_apply(cz(W.shape[1], b, b), Re, C)) if i < L - 1 else 0.0
-                cache[key] = (t_h, t_q, t_e, t_k)
-                n_shapes += 1
-            t_h, t_q, t_e, t_k = cache[key]
+            if key in cache:
+                continue
+            Le, Re, A = cz(W.shape[0], a, a), cz(W.shape[1], b, b), cz(a, d, d, b)
+            C, Lb = cz(b, b), cz(W.shape[1], b, b)
+            t_h = timed(lambda: T.heff_apply(Le, W, Re, A))
+            t_q = timed(lambda: T.qr_pos(A.reshape(a * d * d, b)))
+            t_e = timed(lambda: T.left_env(Le, A, W, A))
+            t_k = timed(lambda: T.keff_apply(Lb, Re, C)) if i < L - 1 else 0.0
+            cache[key] = (t_h, t_q, t_e, t_k)
+    return cache, time.perf_counter() - t_sample
+
+
+def assemble_pair_step(wl, states, times, krylov_mean):
+    """Seconds of one oracle pair-step from the kernel times: one state-step
+    visits every site twice (left-to-right, right-to-left sweep); a visit is
+    krylov_mean H_eff matvecs (the GPU run's mean Krylov vectors per
+    exponential), one gauge QR, one environment update and krylov_mean K_eff
+    matvecs on the bond; a pair-step is both states plus one overlap (one
+    transfer step per site)."""
+    from oracle import mpo as OM
+    Hw = OM.hamiltonian_mpo(wl.model)
+    t_step = 0.0
+    for bonds in states:
+        L = len(Hw)
+        for i in range(L):
+            a = 1 if i == 0 else bonds[i - 1]
+            b = 1 if i == L - 1 else bonds[i]
+            t_h, t_q, t_e, t_k = times[(a, b, Hw[i].shape)]
             t_step += 2 * (krylov_mean * (t_h + t_k) + t_q + t_e) + t_e / len(states)
-    el = time.perf_counter() - t_sample
+    return t_step
+
+
+def cpu_baseline(wl, states, krylov_mean, rep_s=0.25):
+    """The oracle's time for one pair-step of this workload, assembled from
+    the oracle's own kernels timed on this host at every distinct site shape
+    of the two states as they enter the timed steps (not extrapolated from
+    one shape)."""
+    times, el = oracle_kernel_times(wl, states, rep_s)
+    t_step = assemble_pair_step(wl, states, times, krylov_mean)
     cores, blas = blas_info()
     return {"value": 1.0 / t_step, "unit": "pair-steps/s", "cores": cores, "kind": "oracle",
             "blas": blas, "seconds_per_pair_step": t_step,
             "sample": f"oracle H_eff, K_eff, environment and QR kernels timed at each of the "
-                      f"{n_shapes} distinct site shapes of the two prepared states "
+                      f"{len(times)} distinct site shapes of the two prepared states "
                       f"({el:.1f} s of CPU work), assembled into one pair-step with "
                       f"{krylov_mean:.2f} Krylov vectors per exponential (the GPU run's mean)"}
 
@@ -282,7 +364,7 @@ def mu_window(C, dt, beta, c0):
     return float(beta * dt * (c.real.sum() - 0.5 * (c[0].real + c[-1].real)))
 
 
-def roofline_entries(st, peak_of_kind):
+def roofline_entries(st, peak_of_kind, workload_name):
     out = []
     for k in range(32):
         n = st["kind_launches"][k]
@@ -291,6 +373,7 @@ def roofline_entries(st, peak_of_kind):
         ach = st["kind_flops"][k] / st["kind_ms"][k] / 1e9
         peak = peak_of_kind(k)
         out.append({"kernel": kernel_name(k), "launches": n,
+                    "traffic": measured_traffic(kernel_name(k), workload_name),
                     "avg_launch_ms": st["kind_ms"][k] / n,
                     "achieved": ach, "peak": peak, "frac": ach / peak,
                     "algorithmic_flops_per_launch": st["kind_flops"][k] / n,
@@ -324,9 +407,22 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("KIND", "CSV", "LOG"),
                     help="summarise rocprofv3 CSV rows (KIND trace or pmc) of the timed window "
                          "recorded in LOG, then exit (no GPU)")
+    ap.add_argument("--traffic", nargs=4,
+                    metavar=("FETCH_CSV", "FETCH_LOG", "WRITE_CSV", "WRITE_LOG"),
+                    help="write profiles/traffic_<workload>.json from a FETCH_SIZE and a "
+                         "WRITE_SIZE counter pass of this script (run with "
+                         "--calibration-copy-mib), then exit (no GPU)")
+    ap.add_argument("--traffic-commands", nargs="*", default=[],
+                    help="the commands of the two counter passes, recorded with --traffic")
     args = ap.parse_args()
     if args.summarize:
         summarize(*args.summarize)
+        return
+    if args.traffic:
+        rec = traffic_record(*args.traffic, workload(args.workload).name, args.traffic_commands)
+        with open(_traffic_path(rec["workload"]), "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps({k: v["traffic_bytes_per_launch"] for k, v in rec["kernels"].items()}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -428,7 +524,7 @@ def main():
                        "algorithmic_flops_per_launch":
                            st["dom_flops"] / max(st["dom_launches"], 1),
                        "mfma_executed_frac": achieved / peak * (0.75 if dom >> 3 == 1 else 1.0)}
-    out["roofline_all"] = roofline_entries(st, peak_of_kind)
+    out["roofline_all"] = roofline_entries(st, peak_of_kind, wl.name)
     ncmp = max(1, min(args.compare_steps, args.steps))
     refs = {}
     if not args.no_fp64:
@@ -450,7 +546,7 @@ def main():
         bx = {"steps_per_s": ncmp / elb, "ms_per_step": elb / ncmp * 1e3,
               "heff_tflops": stb["heff_flops"] / max(stb["heff_ms"], 1e-9) / 1e9,
               "whole_step_tflops": stb["all_flops"] / elb / 1e12,
-              "roofline_all": roofline_entries(stb, peak_of_kind)}
+              "roofline_all": roofline_entries(stb, peak_of_kind, wl.name)}
         if "c128" in refs:
             bx["c_rel_err_vs_fp64"] = c_err(Cb, refs["c128"], c0)
             mu64 = mu_window(refs["c128"], r.dt, r.beta, c0)
