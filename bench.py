@@ -402,6 +402,10 @@ def main():
                          "profiler region (HBM counter calibration)")
     ap.add_argument("--verbose", type=int, default=1,
                     help="library progress lines on stderr (0 silent, 2 per compression)")
+    ap.add_argument("--state-cache", default=None, metavar="DIR",
+                    help="load Psi_beta and j Psi_beta of this workload from DIR when a "
+                         "previous run saved them there, else prepare them and save them "
+                         "(lets profiled runs skip the preparation)")
     ap.add_argument("--krylov-tol", type=float, default=None,
                     help="Lanczos stop tolerance of the mixed runs (default: the workload's)")
     ap.add_argument("--summarize", nargs=3, metavar=("KIND", "CSV", "LOG"),
@@ -445,20 +449,41 @@ def main():
     tol = args.krylov_tol if args.krylov_tol is not None else r.krylov_tol
     mmax = r.krylov_mmax
 
-    log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D}, "
-        f"{r.prep_precision} contractions, Krylov tol {r.prep_krylov_tol:g}, "
-        f"expansion {r.expand_tol:g})")
-    t0 = time.perf_counter()
-    psi_beta, logz = api.thermal_prep(ctx, H, r.beta, r.n_imag, r.n_grow, r.D, cutoff=r.cutoff,
-                                      precision=r.prep_precision, tol=r.prep_krylov_tol,
-                                      mmax=mmax, expand_tol=r.expand_tol)
-    t_prep = time.perf_counter() - t0
+    cache, cached = None, False
+    if args.state_cache:
+        os.makedirs(args.state_cache, exist_ok=True)
+        cache = {k: os.path.join(args.state_cache, f"{wl.name}_{k}")
+                 for k in ("psi.ftd", "phi.ftd", "meta.json")}
+    if cache and os.path.exists(cache["meta.json"]):
+        with open(cache["meta.json"]) as f:
+            meta = json.load(f)
+        psi_beta = api.mps_load(ctx, cache["psi.ftd"])
+        phi0 = api.mps_load(ctx, cache["phi.ftd"])
+        logz, t_prep, t_j = meta["ln_Z"], meta["prep_s"], meta["jcompress_s"]
+        cached = True
+        log(f"[bench] Psi_beta and j|Psi> loaded from {args.state_cache} (prepared in "
+            f"{t_prep:.1f} s + {t_j:.1f} s by an earlier run)")
+    else:
+        log(f"[bench] {wl.name}: preparing Psi_beta ({r.n_imag} imaginary steps, D={r.D}, "
+            f"{r.prep_precision} contractions, Krylov tol {r.prep_krylov_tol:g}, "
+            f"expansion {r.expand_tol:g})")
+        t0 = time.perf_counter()
+        psi_beta, logz = api.thermal_prep(ctx, H, r.beta, r.n_imag, r.n_grow, r.D,
+                                          cutoff=r.cutoff, precision=r.prep_precision,
+                                          tol=r.prep_krylov_tol, mmax=mmax,
+                                          expand_tol=r.expand_tol)
+        t_prep = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        phi0 = api.apply_compress(ctx, J, psi_beta, r.D, r.cutoff)
+        t_j = time.perf_counter() - t0
+        if cache:
+            psi_beta.save(cache["psi.ftd"])
+            phi0.save(cache["phi.ftd"])
+            with open(cache["meta.json"], "w") as f:
+                json.dump({"ln_Z": logz, "prep_s": t_prep, "jcompress_s": t_j}, f)
     bonds = psi_beta.info()["bond_dims"]
     log(f"[bench] prep {t_prep:.1f} s, ln Z = {logz:.6f}, bonds max {max(bonds)} "
         f"mean {sum(bonds) / len(bonds):.1f}")
-    t0 = time.perf_counter()
-    phi0 = api.apply_compress(ctx, J, psi_beta, r.D, r.cutoff)
-    t_j = time.perf_counter() - t0
     pbonds = phi0.info()["bond_dims"]
     log(f"[bench] j|Psi> compressed in {t_j:.1f} s, bonds max {max(pbonds)} "
         f"mean {sum(pbonds) / len(pbonds):.1f}")
@@ -508,7 +533,7 @@ def main():
         "whole_step_tflops": st["all_flops"] / el_mix / 1e12,
         "matvecs_per_step": st["matvecs"] / args.steps,
         "krylov_mean": st["krylov_vectors"] / max(st["expm_calls"], 1),
-        "prep_s": t_prep, "jcompress_s": t_j, "ln_Z": logz,
+        "prep_s": t_prep, "jcompress_s": t_j, "ln_Z": logz, "state_from_cache": cached,
     }
     dom = st["dom_kind"]
     dom_avg_ms = st["dom_ms"] / max(st["dom_launches"], 1)
