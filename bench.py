@@ -381,6 +381,65 @@ def roofline_entries(st, peak_of_kind, workload_name):
     return sorted(out, key=lambda e: -e["avg_launch_ms"] * e["launches"])
 
 
+def kernel_only(n_repeat=200):
+    """The H_eff matvec alone, repeated, at the benchmark's phonon-site shape
+    (D x d x d x D = 128 x 10 x 10 x 128 with the bulk MPO channels of the
+    rubrene-shaped ring; a 3-molecule ring has the same site), with random
+    site and environment tensors, in each contraction precision: the
+    library's device timing of every GEMM instance, as one JSON line."""
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2003_13245_amd import api
+    from paper_2003_13245_amd import workloads as W
+    wl = W.rubrene_shaped(n_mol=3)
+    ctx = api.Context(0)
+    H, _ = api.mpo_build(ctx, wl.model)
+    dims, _ = H.info()
+    L = len(dims)
+    site = next(i for i in range(L // 2, L) if dims[i] > 2)
+    rng = np.random.default_rng(5)
+    bonds = [min(128, int(min(float(np.prod(dims[: i + 1].astype(float)) ** 2),
+                              float(np.prod(dims[i + 1:].astype(float)) ** 2)))) for i in range(L - 1)]
+    # Gaussian tensors scaled so that every transfer step keeps the
+    # environments of order one (values do not change the timing, overflow
+    # would only make the output unreadable)
+    tensors = []
+    for i in range(L):
+        a, b = 1 if i == 0 else bonds[i - 1], 1 if i == L - 1 else bonds[i]
+        t = W.random_site_tensor(rng, a, int(dims[i]), b)
+        tensors.append(t / np.sqrt(2.0 * a * int(dims[i]) ** 2))
+    x = tensors[site]
+    out = {"mode": "kernel-only", "site_shape": list(x.shape), "repeats": n_repeat}
+    for prec, peak in (("c64", PEAK["c64"]), ("bf16x3", PEAK["bf16"]), ("c128", PEAK["c128"])):
+        g = api.mps_from_host(ctx, tensors)
+        g.set_precision(prec)
+        api.heff_apply(ctx, H, g, site, x, n_repeat=5)
+        ctx.stats_reset()
+        ctx.set_timing(True)
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        api.heff_apply(ctx, H, g, site, x, n_repeat=n_repeat)
+        ctx.synchronize()
+        el = time.perf_counter() - t0
+        st = ctx.stats()
+        ctx.set_timing(False)
+        res = {"wall_ms_per_matvec": el / n_repeat * 1e3,
+               "heff_tflops": st["heff_flops"] / max(st["heff_ms"], 1e-9) / 1e9, "kernels": []}
+        for k in range(32):
+            n = st["kind_launches"][k]
+            if n:
+                ach = st["kind_flops"][k] / st["kind_ms"][k] / 1e9
+                res["kernels"].append({"kernel": kernel_name(k), "launches": n,
+                                       "avg_us": st["kind_ms"][k] / n * 1e3,
+                                       "gflop_per_launch": st["kind_flops"][k] / n / 1e9,
+                                       "achieved": ach, "peak": peak, "frac": ach / peak})
+        out[prec] = res
+        log(f"[bench] kernel-only {prec}: {res['wall_ms_per_matvec']:.3f} ms per matvec")
+        del g
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,6 +475,9 @@ def main():
                     help="write profiles/traffic_<workload>.json from a FETCH_SIZE and a "
                          "WRITE_SIZE counter pass of this script (run with "
                          "--calibration-copy-mib), then exit (no GPU)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="time the H_eff contraction kernels alone at the benchmark's "
+                         "phonon-site shape in every precision (one JSON line), then exit")
     ap.add_argument("--traffic-commands", nargs="*", default=[],
                     help="the commands of the two counter passes, recorded with --traffic")
     args = ap.parse_args()
@@ -427,6 +489,9 @@ def main():
         with open(_traffic_path(rec["workload"]), "w") as f:
             json.dump(rec, f, indent=1)
         print(json.dumps({k: v["traffic_bytes_per_launch"] for k, v in rec["kernels"].items()}))
+        return
+    if args.kernel_only:
+        kernel_only()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
