@@ -145,8 +145,7 @@ void k_convert_f64_f32(Ctx* ctx, const double* src, float* dst, int64_t n);
 void k_scale_cplx(Ctx* ctx, double* x, int64_t n, int64_t plane, double re, double im);
 void k_scale_by_dev(Ctx* ctx, double* x, int64_t n, int64_t plane, const double* s, int inv);
 void k_zero(Ctx* ctx, void* p, size_t bytes);
-// partial sums for <x,y> (complex) and |x|^2; result into dev out[0..1]
-void k_dot(Ctx* ctx, const double* x, const double* y, int64_t n, int64_t plane, double* out);
+// out[0] = |x|^2 (device)
 void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out);
 // h[j] = <V_j, w>, j < k; V_j at V + j*vstride
 void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double* w, int64_t n,

@@ -2,10 +2,10 @@
 //
 //  * qr_chol / lq_chol: shifted CholeskyQR in three passes for the gauge
 //    moves of the sweep (full-rank tall/wide blocks).  Every pass is a Gram
-//    GEMM, a one-workgroup Cholesky and triangular inverse (blocked for
-//    16 <= n <= 128) and an update GEMM; the R factors multiply to an upper
-//    factor with a real positive diagonal, i.e. the unique QR of a full-rank
-//    matrix.
+//    GEMM, a one-workgroup Cholesky and triangular inverse (held in
+//    registers for n <= 128) and an update GEMM; the R factors multiply to an
+//    upper factor with a real positive diagonal, i.e. the unique QR of a
+//    full-rank matrix.
 //  * qr_householder: blocked Householder QR (compact WY) for matrices of any
 //    rank; used by the compressions, where MPO x MPS products are rank
 //    deficient.  Column-major working copy; panel columns are reflected with

@@ -115,23 +115,6 @@ void k_zero(Ctx* ctx, void* p, size_t bytes) {
 }
 
 // --------------------------------------------------------------- reductions
-__global__ void dot_partial(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
-                            int64_t plane, double* __restrict__ part) {
-    __shared__ double sh[16];
-    double sr = 0.0, si = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double xr = x[i], xi = x[i + plane], yr = y[i], yi = y[i + plane];
-        sr += xr * yr + xi * yi;
-        si += xr * yi - xi * yr;
-    }
-    sr = block_sum(sr, sh);
-    si = block_sum(si, sh);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = sr;
-        part[2 * blockIdx.x + 1] = si;
-    }
-}
 __global__ void nrm2_partial(const double* __restrict__ x, int64_t n, int64_t plane,
                              double* __restrict__ part, const int* stop) {
     if (stop && *stop) return;
@@ -164,14 +147,6 @@ __global__ void sum_partials(const double* __restrict__ part, int nb, int width,
     }
 }
 
-void k_dot(Ctx* ctx, const double* x, const double* y, int64_t n, int64_t plane, double* out) {
-    const int nb = red_blocks(n);
-    ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
-    double* part = ctx->ws_red.as<double>();
-    dot_partial<<<nb, RB, 0, ctx->stream>>>(x, y, n, plane, part);
-    sum_partials<<<1, RB, 0, ctx->stream>>>(part, nb, 2, out, nullptr);
-    FTD_HIP(hipGetLastError());
-}
 void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out) {
     const int nb = red_blocks(n);
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
