@@ -231,6 +231,8 @@ def workload(name):
         return W.rubrene_shaped(n_mol=5, n_loc=2, n_nl=1, levels=6, D=32, n_imag=8)
     if name == "medium":
         return W.rubrene_shaped(n_mol=11, n_loc=4, n_nl=1, levels=10, D=64, n_imag=16)
+    if name == "large":
+        return W.large_rubrene_shaped()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -381,24 +383,29 @@ def roofline_entries(st, peak_of_kind, workload_name):
     return sorted(out, key=lambda e: -e["avg_launch_ms"] * e["launches"])
 
 
-def kernel_only(n_repeat=200):
-    """The H_eff matvec alone, repeated, at the benchmark's phonon-site shape
-    (D x d x d x D = 128 x 10 x 10 x 128 with the bulk MPO channels of the
-    rubrene-shaped ring; a 3-molecule ring has the same site), with random
-    site and environment tensors, in each contraction precision: the
-    library's device timing of every GEMM instance, as one JSON line."""
+def kernel_only(workload_name, n_repeat=200):
+    """The H_eff matvec alone, repeated, at the workload's phonon-site shape
+    (headline: D x d x d x D = 128 x 10 x 10 x 128; large: 256 x 12 x 12 x
+    256) with the bulk MPO channels of the rubrene-shaped ring (a 3-molecule
+    ring of the same modes has the same site), with random site and
+    environment tensors, in each contraction precision: the library's device
+    timing of every GEMM instance, as one JSON line."""
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2003_13245_amd import api
     from paper_2003_13245_amd import workloads as W
-    wl = W.rubrene_shaped(n_mol=3)
+    if workload_name == "large":
+        wl = W.rubrene_shaped(n_mol=3, n_loc=6, n_nl=2, levels=12, D=256)
+    else:
+        wl = W.rubrene_shaped(n_mol=3)
+    Dmax = wl.run.D
     ctx = api.Context(0)
     H, _ = api.mpo_build(ctx, wl.model)
     dims, _ = H.info()
     L = len(dims)
     site = next(i for i in range(L // 2, L) if dims[i] > 2)
     rng = np.random.default_rng(5)
-    bonds = [min(128, int(min(float(np.prod(dims[: i + 1].astype(float)) ** 2),
+    bonds = [min(Dmax, int(min(float(np.prod(dims[: i + 1].astype(float)) ** 2),
                               float(np.prod(dims[i + 1:].astype(float)) ** 2)))) for i in range(L - 1)]
     # Gaussian tensors scaled so that every transfer step keeps the
     # environments of order one (values do not change the timing, overflow
@@ -409,7 +416,8 @@ def kernel_only(n_repeat=200):
         t = W.random_site_tensor(rng, a, int(dims[i]), b)
         tensors.append(t / np.sqrt(2.0 * a * int(dims[i]) ** 2))
     x = tensors[site]
-    out = {"mode": "kernel-only", "site_shape": list(x.shape), "repeats": n_repeat}
+    out = {"mode": "kernel-only", "workload": workload_name, "site_shape": list(x.shape),
+           "repeats": n_repeat}
     for prec, peak in (("c64", PEAK["c64"]), ("bf16x3", PEAK["bf16"]), ("c128", PEAK["c128"])):
         g = api.mps_from_host(ctx, tensors)
         g.set_precision(prec)
@@ -476,8 +484,10 @@ def main():
                          "WRITE_SIZE counter pass of this script (run with "
                          "--calibration-copy-mib), then exit (no GPU)")
     ap.add_argument("--kernel-only", action="store_true",
-                    help="time the H_eff contraction kernels alone at the benchmark's "
-                         "phonon-site shape in every precision (one JSON line), then exit")
+                    help="time the H_eff contraction kernels alone at the phonon-site "
+                         "shape of --workload (large: 256x12x12x256, otherwise the "
+                         "headline's 128x10x10x128) in every precision (one JSON line), "
+                         "then exit")
     ap.add_argument("--traffic-commands", nargs="*", default=[],
                     help="the commands of the two counter passes, recorded with --traffic")
     args = ap.parse_args()
@@ -491,7 +501,7 @@ def main():
         print(json.dumps({k: v["traffic_bytes_per_launch"] for k, v in rec["kernels"].items()}))
         return
     if args.kernel_only:
-        kernel_only()
+        kernel_only(args.workload, n_repeat=200 if args.workload != "large" else 30)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
