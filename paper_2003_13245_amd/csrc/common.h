@@ -151,12 +151,16 @@ void k_nrm2(Ctx* ctx, const double* x, int64_t n, int64_t plane, double* out);
 void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double* w, int64_t n,
                 int64_t plane, double* h, double* alpha = nullptr);
 // w -= sum_j V_j h[j] in one pass, with |w|^2 left as block partials in ctx->ws_red;
-// returns their count
+// returns their count.  With `skip` (two device doubles: |w|^2 after and before
+// the first Gram-Schmidt pass) the kernel does nothing when skip[0] > thr2 *
+// skip[1], the test the tridiagonal kernel repeats to pick its norm
 int k_multiaxpy_nrm2_part(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
-                          double* w, int64_t n, int64_t plane);
+                          double* w, int64_t n, int64_t plane, const double* skip = nullptr,
+                          double thr2 = 0.0);
 // w -= sum_j V_j h[j], then h[j] = <V_j, w> of the updated w, in one pass over
-// V and w; false (nothing done) when k or n is outside its range (k <= 16,
-// long vectors), so that the caller falls back to k_multiaxpy + k_multidot
+// V and w; also h[k] = (|w|^2 after, |w|^2 before the update).  False (nothing
+// done) when k or n is outside its range (k <= 16, long vectors), so that the
+// caller falls back to k_multiaxpy + k_multidot
 bool k_multiaxpy_dot(Ctx* ctx, const double* V, int64_t vstride, int k, double* h, double* w,
                      int64_t n, int64_t plane);
 // w -= sum_j V_j h[j]
@@ -189,9 +193,12 @@ struct KrylovDev {
     double* nrm;     // [4]
     int* flag;       // [4]: converged, k, failed, halt (converged or failed)
 };
-// the squared norm of the new residual is given as `nb` block partials
+// the squared norm of the new residual is given as `nb` block partials, or,
+// when skip[0] > thr2 * skip[1] (the second Gram-Schmidt pass was skipped), as
+// skip[0]
 void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
-                    int exhausted, const double* nrm_part, int nb);
+                    int exhausted, const double* nrm_part, int nb, const double* skip = nullptr,
+                    double thr2 = 0.0);
 void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane,
                     float* out32 = nullptr);
 void k_set_alpha(Ctx* ctx, KrylovDev kd, int k);

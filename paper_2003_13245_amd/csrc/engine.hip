@@ -8,6 +8,7 @@
 // (real plane, then imaginary plane).  Environments hold one D x D block per
 // MPO channel, each block [re plane][im plane].
 #include <algorithm>
+#include <cfloat>
 #include <exception>
 #include <functional>
 #include <numeric>
@@ -700,6 +701,9 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
     std::vector<int64_t> mv_mark(kmax + 1);
     std::vector<double> fl_mark(kmax + 1);
     ctx->kstop = kd.flag + 3;
+    // 100 u / tol (u = 2^-53): a tolerance of about 1e-14 or tighter keeps
+    // both Gram-Schmidt passes always
+    const double cgs_thr = tol > 0.0 ? 100.0 * 0.5 * DBL_EPSILON / tol : 1.0;
     int done = 0;
     try {
         for (int k = 0; k < kmax; ++k) {
@@ -710,16 +714,23 @@ static int expm_krylov(Ctx* ctx, const std::function<void(const double*, double*
             double* w = V + (int64_t)(k + 1) * vs;
             ctx->last32_x = nullptr;
             op(vk, w);
-            // classical Gram-Schmidt twice; alpha_k = <v_k, w> of the first pass
+            // classical Gram-Schmidt twice; alpha_k = <v_k, w> of the first pass.
+            // The second correction is skipped on the device when the first
+            // pass kept more than thr of |w| (then its orthogonality error,
+            // about u |w| / |w'|, is below tol / 100).
             k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h, kd.alpha + k);
-            if (!k_multiaxpy_dot(ctx, V, vs, k + 1, kd.h, w, n, n)) {
+            const double* skip = nullptr;
+            if (k_multiaxpy_dot(ctx, V, vs, k + 1, kd.h, w, n, n)) {
+                if (cgs_thr < 0.5) skip = kd.h + 2 * (k + 1);
+            } else {
                 k_multiaxpy(ctx, V, vs, k + 1, kd.h, w, n, n);
                 k_multidot(ctx, V, vs, k + 1, w, n, n, kd.h);
             }
-            const int nb = k_multiaxpy_nrm2_part(ctx, V, vs, k + 1, kd.h, w, n, n);
+            const double thr2 = cgs_thr * cgs_thr;
+            const int nb = k_multiaxpy_nrm2_part(ctx, V, vs, k + 1, kd.h, w, n, n, skip, thr2);
             const int exhausted = (k + 1 == n) ? 1 : 0;
             k_tridiag_expm(ctx, kd, k + 1, z.real(), z.imag(), tol, exhausted,
-                           ctx->ws_red.as<double>(), nb);
+                           ctx->ws_red.as<double>(), nb, skip, thr2);
             // the normalised w is the next matvec's input: when the matvec just
             // loaded its input as a float copy, the normalisation writes the
             // next one in the same place

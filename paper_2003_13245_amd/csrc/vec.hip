@@ -202,7 +202,8 @@ __global__ __launch_bounds__(RB) void multidot_w1_partial(const double* __restri
 
 // One pass of w -= sum_j V_j h[j] (j < k <= KC) that also forms the block
 // partials of the next projections <V_j, w> of the updated w (the second
-// Gram-Schmidt pass needs exactly these), part[(j * nb + b) * 2].
+// Gram-Schmidt pass needs exactly these), part[(j * nb + b) * 2], and in group
+// k the partials of |w|^2 after and before the update.
 template <int KC>
 __global__ __launch_bounds__(RB) void multiaxpy_dot_partial(const double* __restrict__ V,
                                                            int64_t vstride, int k,
@@ -220,10 +221,12 @@ __global__ __launch_bounds__(RB) void multiaxpy_dot_partial(const double* __rest
         hi[j] = j < k ? h[2 * j + 1] : 0.0;
         sr[j] = si[j] = 0.0;
     }
+    double s_before = 0.0, s_after = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double vr[KC], vi[KC];
         double ar = w[i], ai = w[i + plane];
+        s_before += ar * ar + ai * ai;
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
             if (j < k) {
@@ -235,6 +238,7 @@ __global__ __launch_bounds__(RB) void multiaxpy_dot_partial(const double* __rest
         }
         w[i] = ar;
         w[i + plane] = ai;
+        s_after += ar * ar + ai * ai;
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
             if (j < k) {
@@ -244,6 +248,12 @@ __global__ __launch_bounds__(RB) void multiaxpy_dot_partial(const double* __rest
         }
     }
     block_sums_out<KC>(sr, si, k, 0, part, sh);
+    const double a = block_sum(s_after, sh), b = block_sum(s_before, sh);
+    if (threadIdx.x == 0) {
+        const int64_t o = ((int64_t)k * gridDim.x + blockIdx.x) * 2;
+        part[o] = a;
+        part[o + 1] = b;
+    }
 }
 
 // h[j] = <V_j, w>: grid (nb, k)
@@ -301,17 +311,19 @@ bool k_multiaxpy_dot(Ctx* ctx, const double* V, int64_t vstride, int k, double* 
     else
         multiaxpy_dot_partial<16><<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
                                                               ctx->kstop);
-    sum_partials<<<k, RB, 0, ctx->stream>>>(part, nb, 2, h, ctx->kstop);
+    sum_partials<<<k + 1, RB, 0, ctx->stream>>>(part, nb, 2, h, ctx->kstop);
     FTD_HIP(hipGetLastError());
     return true;
 }
 
-// w -= sum_j V_j h[j], then block partials of |w|^2 (one pass over w)
+// w -= sum_j V_j h[j], then block partials of |w|^2 (one pass over w); not
+// at all when the first pass kept enough of w (skip[0] > thr2 * skip[1])
 __global__ void multiaxpy_nrm_partial(const double* __restrict__ V, int64_t vstride, int k,
                                       const double* __restrict__ h, double* __restrict__ w,
                                       int64_t n, int64_t plane, double* __restrict__ part,
-                                      const int* stop) {
+                                      const int* stop, const double* skip, double thr2) {
     if (stop && *stop) return;
+    if (skip && skip[0] > thr2 * skip[1]) return;
     __shared__ double sh[16];
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -331,12 +343,12 @@ __global__ void multiaxpy_nrm_partial(const double* __restrict__ V, int64_t vstr
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 int k_multiaxpy_nrm2_part(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
-                          double* w, int64_t n, int64_t plane) {
+                          double* w, int64_t n, int64_t plane, const double* skip, double thr2) {
     const int nb = red_blocks(n);
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
     multiaxpy_nrm_partial<<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
-                                                      ctx->kstop);
+                                                      ctx->kstop, skip, thr2);
     FTD_HIP(hipGetLastError());
     return nb;
 }
@@ -604,17 +616,24 @@ __device__ __forceinline__ double lane_get(double v, int i) {
 }
 
 // The squared norm of the new Lanczos residual arrives as `nb` block
-// partials (summed here in a fixed order, and stored to kd.nrm[0]).
+// partials (summed here in a fixed order, and stored to kd.nrm[0]), or as
+// skip[0] when the second Gram-Schmidt pass was skipped (the same test as in
+// multiaxpy_nrm_partial).
 __global__ __launch_bounds__(64) void tridiag_expm_kernel(KrylovDev kd, int n, double zr,
                                                           double zi, double tol, int exhausted,
                                                           int mmax, const double* nrm_part,
-                                                          int nb) {
+                                                          int nb, const double* skip,
+                                                          double thr2) {
     __shared__ double Z[kMaxKrylov][kMaxKrylov + 1];
     if (kd.flag[3]) return;   // an earlier iteration converged or failed
     const int j = threadIdx.x;
     double nsq = 0.0;
-    for (int b = j; b < nb; b += 64) nsq += nrm_part[b];
-    for (int o = 32; o > 0; o >>= 1) nsq += __shfl_xor(nsq, o, 64);
+    if (skip && skip[0] > thr2 * skip[1]) {
+        nsq = skip[0];
+    } else {
+        for (int b = j; b < nb; b += 64) nsq += nrm_part[b];
+        for (int o = 32; o > 0; o >>= 1) nsq += __shfl_xor(nsq, o, 64);
+    }
     if (j == 0) kd.nrm[0] = nsq;
     const double bnew = sqrt(fmax(nsq, 0.0));
     double dj = (j < n) ? kd.alpha[j] : 0.0;
@@ -744,9 +763,10 @@ void k_krylov_reset(Ctx* ctx, KrylovDev kd) {
 }
 
 void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double tol,
-                    int exhausted, const double* nrm_part, int nb) {
+                    int exhausted, const double* nrm_part, int nb, const double* skip,
+                    double thr2) {
     tridiag_expm_kernel<<<1, 64, 0, ctx->stream>>>(kd, k, zr, zi, tol, exhausted, kMaxKrylov,
-                                                   nrm_part, nb);
+                                                   nrm_part, nb, skip, thr2);
     FTD_HIP(hipGetLastError());
 }
 void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane,
