@@ -116,6 +116,32 @@ def test_one_tdvp_step(ctx, kind, levels):
     assert dist < 1e-11, dist
 
 
+@pytest.mark.parametrize("tol,bound", [(1e-14, 1e-11), (1e-10, 1e-8)])
+def test_one_tdvp_step_long_vectors(ctx, tol, bound):
+    """A real TDVP step at sites whose vectors take the fused Gram-Schmidt
+    kernels (48 x 8 x 8 x 48 = 147456 elements).  At tol 1e-14 both passes
+    always run; at 1e-10 the second pass is skipped unless the first cancels
+    more than about six digits, and the step still follows the oracle's
+    (tol 1e-14, both passes) to the Krylov tolerance."""
+    from paper_2003_13245_amd import api
+    m = small_model(n_mol=3, n_loc=1, n_nl=1, levels=8)
+    dims = Mdl.site_dims(m)
+    Hw = OM.hamiltonian_mpo(m)
+    H, J = api.mpo_build(ctx, m)
+    rng = np.random.default_rng(17)
+    psi = random_mps(dims, 48, rng, 0)
+    assert max(int(np.prod(a.shape)) for a in psi.A) >= 16384
+    g = api.mps_from_host(ctx, psi.A)
+    say(f"[tdvp long] tol={tol:g}")
+    T.tdvp_step(psi, Hw, -1j * 0.1)
+    api.tdvp_step(ctx, H, g, dt_real=0.1, tol=tol)
+    got = gpu_tensors(g, dims)
+    assert got.bond_dims() == psi.bond_dims(), (got.bond_dims(), psi.bond_dims())
+    dist = mps_rel_distance(got, psi)
+    say(f"[tdvp long] tol={tol:g} distance {dist:.3e}")
+    assert dist < bound, dist
+
+
 @pytest.mark.parametrize("D", [3, 8, 64])
 def test_pc_stage(ctx, D):
     """psi + c H phi SVD-compressed, against the oracle."""
