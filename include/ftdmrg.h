@@ -88,9 +88,12 @@ typedef struct {
     double e0;
 } ftd_model;
 
-/* Krylov exponential settings: Lanczos with full reorthogonalisation (float64),
- * stopped when beta_k |e_k^T exp(zT_k) e_1| <= tol |exp(zT_k) e_1| or when
- * the Krylov space is exhausted; more than mmax vectors -> FTD_ENOCONV. */
+/* Krylov exponential settings: Lanczos with full reorthogonalisation (float64,
+ * classical Gram-Schmidt; for tol above about 2e-14 the second pass runs only
+ * when the first left at most 100 u / tol of the residual's norm, u = 2^-53,
+ * so that one pass's orthogonality error stays below tol / 100), stopped when
+ * beta_k |e_k^T exp(zT_k) e_1| <= tol |exp(zT_k) e_1| or when the Krylov
+ * space is exhausted; more than mmax vectors -> FTD_ENOCONV. */
 typedef struct {
     double tol;
     int32_t mmax;
