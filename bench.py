@@ -444,8 +444,74 @@ def kernel_only(workload_name, n_repeat=200):
         out[prec] = res
         log(f"[bench] kernel-only {prec}: {res['wall_ms_per_matvec']:.3f} ms per matvec")
         del g
+    out["lanczos"] = lanczos_only(api, ctx, H, tensors, site, -0.5j * wl.run.dt,
+                                  max(10, n_repeat // 10))
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def lanczos_traffic(n, m):
+    """Algorithmic HBM bytes of the float64 Lanczos vector kernels in one
+    Krylov exponential of m vectors on n complex elements with both
+    Gram-Schmidt passes (one vector pass is 16 n bytes): the projections read
+    w once per eight basis vectors; the fused first correction and second
+    projection, and the second correction with its norm, each read the basis
+    and w and write w; the normalisation reads and writes w (not after the
+    converged iteration); the final combination reads the m vectors and
+    writes the result; the start reads x for its norm, copies it and scales
+    the copy."""
+    v = 16.0 * n
+    t = {"multidot_w1_partial": 0.0, "multiaxpy_dot_partial": 0.0,
+         "multiaxpy_nrm_partial": 0.0, "lanczos_post_kernel": 0.0,
+         "lincomb_kernel": (m + 1) * v, "nrm2_partial+copy_kernel+scale_dev_kernel": 5 * v}
+    for k in range(m):
+        j = k + 1
+        t["multidot_w1_partial"] += (j - (-j // 8)) * v
+        t["multiaxpy_dot_partial"] += (j + 2) * v
+        t["multiaxpy_nrm_partial"] += (j + 2) * v
+        if k < m - 1:
+            t["lanczos_post_kernel"] += 2 * v
+    return t
+
+
+def lanczos_only(api, ctx, H, tensors, site, z, n_exp):
+    """The Krylov exponential exp(z H_eff) x at one site (float64
+    contractions, Krylov tolerance 1e-14, so that both Gram-Schmidt passes
+    always run and every launch's traffic is known), repeated: its Krylov
+    count, wall time per exponential and the algorithmic bytes of each Lanczos
+    kernel per exponential.  Divided by the kernels' total times in a kernel
+    trace of the same command (over all 2 + n_exp exponentials it runs) they
+    give the achieved bandwidth."""
+    g = api.mps_from_host(ctx, tensors)
+    g.set_precision("c128")
+    x = tensors[site]
+    try:
+        api.heff_expm(ctx, H, g, site, x, z)   # warm-up: environments, buffers
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        _, m1 = api.heff_expm(ctx, H, g, site, x, z)
+        ctx.synchronize()
+        t1 = time.perf_counter()
+        _, m = api.heff_expm(ctx, H, g, site, x, z, n_repeat=n_exp)
+        ctx.synchronize()
+        t2 = time.perf_counter()
+    except api.FtdError as e:
+        return {"error": str(e)}
+    finally:
+        del g
+    # both calls build the same environments: their difference is n_exp - 1
+    # exponentials
+    per = ((t2 - t1) - (t1 - t0)) / (n_exp - 1)
+    n = int(np.prod(x.shape))
+    traffic = lanczos_traffic(n, m)
+    res = {"precision": "c128", "z": [z.real, z.imag], "krylov_vectors": m,
+           "krylov_vectors_first": m1, "exponentials_total": 2 + n_exp,
+           "wall_ms_per_exp": per * 1e3, "vector_bytes": 16 * n,
+           "bytes_per_exp": traffic,
+           "lanczos_bytes_per_exp": sum(traffic.values())}
+    log(f"[bench] kernel-only Lanczos: m = {m}, {per * 1e3:.3f} ms per exponential, "
+        f"{res['lanczos_bytes_per_exp'] / 1e9:.2f} GB of vector traffic")
+    return res
 
 
 def main():

@@ -406,6 +406,19 @@ ftd_status ftd_coherent_length(const double* sigma, int32_t n, double* L);
 ftd_status ftd_heff_apply(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, int32_t site,
                           const double* x, double* y, int32_t n_repeat);
 
+/* The local step of the projector-splitting integrator (the paper's
+ * time-dependent variational method: each site tensor is propagated by the
+ * exponential of its effective Hamiltonian): y = exp(z H_eff) x at `site`,
+ * with the environments of ftd_heff_apply and the Krylov exponential of
+ * ftd_tdvp_step (settings `ko`, NULL: tol 1e-14, mmax 40), in psi's
+ * precision.  x, y: host interleaved complex of psi's site shape.  n_repeat
+ * > 1 repeats the exponential from the same x (timing of the Lanczos
+ * kernels).  *m_out (may be NULL) receives the Krylov vector count.  Errors:
+ * FTD_EINVAL (site, lengths, non-finite z, Krylov settings), FTD_ENOCONV. */
+ftd_status ftd_heff_expm(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, int32_t site,
+                         const double* x, double* y, double zr, double zi,
+                         const ftd_krylov_opts* ko, int32_t n_repeat, int32_t* m_out);
+
 /* Gauge move of the TDVP sweep on the device (shifted CholeskyQR in three
  * passes, the orthonormalisation the projector-splitting integrator needs
  * between a site and the next bond): lq = 0: M (rows x cols, rows >= cols,

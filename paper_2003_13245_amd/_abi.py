@@ -107,6 +107,7 @@ SIGNATURES = {
     "ftd_reduced_density": (I32, [P, P, P, DP]),
     "ftd_coherent_length": (I32, [DP, I32, DP]),
     "ftd_heff_apply": (I32, [P, P, P, I32, DP, DP, I32]),
+    "ftd_heff_expm": (I32, [P, P, P, I32, DP, DP, D, D, C.POINTER(KrylovOpts), I32, I32P]),
     "ftd_svd_trunc": (I32, [P, I32, I32, DP, I32, D, I32, DP, DP, I32P]),
     "ftd_qr": (I32, [P, I32, I32, DP, I32, DP, DP]),
     "ftd_gemm": (I32, [P, I32, I32, I32, I32, I32, I32, DP, DP, DP]),

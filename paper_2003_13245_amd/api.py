@@ -556,6 +556,22 @@ def svd_trunc(ctx, T, D, cutoff=1e-10, s_left=True):
     return L, R
 
 
+def heff_expm(ctx, H, psi, site, x, z, tol=1e-14, mmax=40, n_repeat=1):
+    """exp(z H_eff) x at `site` by the library's Krylov exponential; returns
+    (y, Krylov vector count)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    xb = np.empty(2 * x.size)
+    xb[0::2] = x.real.reshape(-1)
+    xb[1::2] = x.imag.reshape(-1)
+    yb = np.zeros_like(xb)
+    m = C.c_int32(0)
+    ko = _abi._krylov(tol, mmax)
+    check(lib.ftd_heff_expm(ctx.h, H.h, psi.h, int(site), _abi._dptr(xb), _abi._dptr(yb),
+                            float(complex(z).real), float(complex(z).imag), C.byref(ko),
+                            int(n_repeat), C.byref(m)))
+    return (yb[0::2] + 1j * yb[1::2]).reshape(x.shape), int(m.value)
+
+
 def heff_apply(ctx, H, psi, site, x, n_repeat=1):
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
     xb = np.empty(2 * x.size)

@@ -1007,6 +1007,21 @@ ftd_status ftd_heff_apply(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, in
     });
 }
 
+ftd_status ftd_heff_expm(ftd_ctx* ctx, const ftd_mpo* H, const ftd_mps* psi, int32_t site,
+                         const double* x, double* y, double zr, double zi,
+                         const ftd_krylov_opts* ko, int32_t n_repeat, int32_t* m_out) {
+    return guarded([&] {
+        FTD_CHECK(ctx && H && psi && x && y, FTD_EINVAL, "null argument");
+        FTD_CHECK(std::isfinite(zr) && std::isfinite(zi), FTD_EINVAL, "non-finite z");
+        double tol;
+        int mmax;
+        check_krylov(ko, tol, mmax);
+        const int m = heff_expm_host(&ctx->c, H->m, psi->m, site, x, y, cplx(zr, zi), tol, mmax,
+                                     n_repeat);
+        if (m_out) *m_out = m;
+    });
+}
+
 ftd_status ftd_svd_trunc(ftd_ctx* ctx, int32_t M, int32_t N, const double* T, int32_t D,
                          double cutoff, int32_t s_left, double* L, double* R, int32_t* kout) {
     return guarded([&] {

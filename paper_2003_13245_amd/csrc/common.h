@@ -389,6 +389,8 @@ double mps_normalize(Ctx* ctx, Mps* psi);
 cplx overlap(Ctx* ctx, const Mps* bra, const Mpo* O, const Mps* ket);
 void heff_apply_host(Ctx* ctx, const Mpo* H, const Mps* psi, int site, const double* x,
                      double* y, int nrep);
+int heff_expm_host(Ctx* ctx, const Mpo* H, const Mps* psi, int site, const double* x, double* y,
+                   cplx z, double tol, int mmax, int nrep);
 
 }  // namespace ftd
 

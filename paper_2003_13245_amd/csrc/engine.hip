@@ -1876,4 +1876,54 @@ void heff_apply_host(Ctx* ctx, const Mpo* H, const Mps* psi, int site, const dou
     dev_free(ctx, dy);
 }
 
+// y = exp(z H_eff) x at one site, by the Krylov exponential of the TDVP
+// sweep (same environments and operator as heff_apply_host); repeated nrep
+// times from the same x (timing).  Returns the Krylov vector count.
+int heff_expm_host(Ctx* ctx, const Mpo* H, const Mps* psi, int site, const double* x, double* y,
+                   cplx z, double tol, int mmax, int nrep) {
+    const int L = psi->L;
+    FTD_CHECK(site >= 0 && site < L, FTD_EINVAL, "site out of range");
+    FTD_CHECK(H->L == L, FTD_EINVAL, "MPO and MPS lengths differ");
+    const Prec prec = psi->prec;
+    build_left_envs(ctx, H, psi, site);
+    build_right_envs(ctx, H, psi, site + 1);
+    const int64_t n = psi->size(site);
+    double* dx0 = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n));
+    double* dx = nullptr;
+    int m = 0;
+    try {
+        dx = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * n));
+        std::vector<double> hx(2 * n);
+        for (int64_t k = 0; k < n; ++k) {
+            hx[k] = x[2 * k];
+            hx[k + n] = x[2 * k + 1];
+        }
+        FTD_HIP(hipMemcpyAsync(dx0, hx.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice,
+                               ctx->stream));
+        EnvView Lv = envL_view(ctx, site, prec), Rv = envR_view(ctx, site + 1, prec);
+        const MpoSite& W = H->s[site];
+        const int Da = psi->Dl[site], Db = psi->Dr[site];
+        auto op = [&](const double* a, double* b) { heff(ctx, prec, W, Da, Db, Lv, Rv, a, b); };
+        int hint = 4;
+        for (int r = 0; r < std::max(1, nrep); ++r) {
+            k_copy_f64(ctx, dx0, dx, 2 * n);
+            m = expm_krylov(ctx, op, dx, n, z, tol, mmax, hint);
+        }
+        FTD_HIP(hipMemcpyAsync(hx.data(), dx, sizeof(double) * 2 * n, hipMemcpyDeviceToHost,
+                               ctx->stream));
+        FTD_HIP(hipStreamSynchronize(ctx->stream));
+        for (int64_t k = 0; k < n; ++k) {
+            y[2 * k] = hx[k];
+            y[2 * k + 1] = hx[k + n];
+        }
+    } catch (...) {
+        dev_free(ctx, dx0);
+        if (dx) dev_free(ctx, dx);
+        throw;
+    }
+    dev_free(ctx, dx0);
+    dev_free(ctx, dx);
+    return m;
+}
+
 }  // namespace ftd

@@ -144,3 +144,18 @@ def test_window_selection(bench, tmp_path, capsys):
     line = [l for l in out.splitlines() if l.endswith("\tk_a")][0]
     calls, total_ms = line.split("\t")[:2]
     assert calls == "2" and float(total_ms) == pytest.approx(50 + 60)
+
+
+def test_lanczos_traffic_counts_vector_passes():
+    """One Krylov vector: projection 2 passes, fused correction 3, second
+    correction 3, no normalisation (the iteration converges), final
+    combination 2, start 5: 15 passes of 16 n bytes; each further vector j
+    adds j + ceil(j / 8) + 2 (j + 2) + 2 passes and one more for the final
+    combination."""
+    import bench
+    n = 1000
+    one = bench.lanczos_traffic(n, 1)
+    assert sum(one.values()) == 15 * 16 * n
+    for m in range(2, 20):
+        d = sum(bench.lanczos_traffic(n, m).values()) - sum(bench.lanczos_traffic(n, m - 1).values())
+        assert d == (m + -(-m // 8) + 2 * (m + 2) + 2 + 1) * 16 * n, m

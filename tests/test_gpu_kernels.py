@@ -144,6 +144,58 @@ def test_one_tdvp_step_long_vectors(ctx, tol, bound):
     assert dist < bound, dist
 
 
+@pytest.mark.parametrize("prec,tol,bound", [("c128", 1e-14, 1e-12), ("c128", 1e-10, 1e-9),
+                                            ("c64", 1e-8, 2e-5)])
+def test_heff_expm_matches_oracle(ctx, prec, tol, bound):
+    """One local exponential exp(z H_eff) x at a 48 x 8 x 8 x 48 site (the
+    projector-splitting integrator's site step) against the oracle's Lanczos
+    with the oracle's H_eff from the same tensors; in float64 at tol 1e-14 the
+    Krylov vector count is the oracle's."""
+    from paper_2003_13245_amd import api
+    m = small_model(n_mol=3, n_loc=1, n_nl=1, levels=8)
+    dims = Mdl.site_dims(m)
+    Hw = OM.hamiltonian_mpo(m)
+    H, J = api.mpo_build(ctx, m)
+    rng = np.random.default_rng(19)
+    site = 4
+    psi = random_mps(dims, 48, rng, site)
+    assert psi.A[site].shape == (48, 8, 8, 48)
+    Lenv = T._boundary(1)
+    for i in range(site):
+        Lenv = T.left_env(Lenv, psi.A[i], Hw[i], psi.A[i])
+    Renv = T._boundary(1)
+    for i in range(len(dims) - 1, site, -1):
+        Renv = T.right_env(Renv, psi.A[i], Hw[i], psi.A[i])
+    x = psi.A[site]
+    z = -0.3j
+    y_ref, m_ref = T.expm_krylov(lambda v: T.heff_apply(Lenv, Hw[site], Renv, v), x, z)
+    g = api.mps_from_host(ctx, psi.A)
+    g.set_precision(prec)
+    say(f"[expm] {prec} tol={tol:g}")
+    y, m_gpu = api.heff_expm(ctx, H, g, site, x, z, tol=tol)
+    err = rel(y, y_ref)
+    say(f"[expm] {prec} tol={tol:g} m={m_gpu} (oracle {m_ref}) err {err:.3e}")
+    assert err < bound, err
+    if prec == "c128" and tol == 1e-14:
+        assert m_gpu == m_ref, (m_gpu, m_ref)
+
+
+def test_heff_expm_rejects_bad_arguments(ctx):
+    from paper_2003_13245_amd import api
+    m = small_model(n_mol=3, n_loc=1, n_nl=0, levels=2)
+    dims = Mdl.site_dims(m)
+    H, J = api.mpo_build(ctx, m)
+    psi = random_mps(dims, 4, np.random.default_rng(2), 0)
+    g = api.mps_from_host(ctx, psi.A)
+    x = psi.A[0]
+    with pytest.raises(api.FtdError):
+        api.heff_expm(ctx, H, g, len(dims), x, -0.1j)
+    with pytest.raises(api.FtdError):
+        api.heff_expm(ctx, H, g, 0, x, complex(float("nan"), 0.0))
+    with pytest.raises(api.FtdError):
+        api.heff_expm(ctx, H, g, 0, x, -0.1j, tol=0.0)
+
+
 @pytest.mark.parametrize("D", [3, 8, 64])
 def test_pc_stage(ctx, D):
     """psi + c H phi SVD-compressed, against the oracle."""
