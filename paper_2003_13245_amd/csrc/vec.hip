@@ -173,9 +173,11 @@ __device__ __forceinline__ void block_sums_out(double (&sr)[KC], double (&si)[KC
     }
 }
 
+// KC is the exact vector count: every load of an element is unconditional,
+// so all 2 KC + 2 of them are in flight together
 template <int KC>
 __global__ __launch_bounds__(RB) void multidot_w1_partial(const double* __restrict__ V,
-                                                         int64_t vstride, int j0, int kc,
+                                                         int64_t vstride, int j0,
                                                          const double* __restrict__ w, int64_t n,
                                                          int64_t plane, double* __restrict__ part,
                                                          const int* stop) {
@@ -187,38 +189,56 @@ __global__ __launch_bounds__(RB) void multidot_w1_partial(const double* __restri
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double wr = w[i], wi = w[i + plane];
+        double vr[KC], vi[KC];
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
-            if (j < kc) {
-                const double* v = V + (int64_t)(j0 + j) * vstride;
-                const double vr = v[i], vi = v[i + plane];
-                sr[j] += vr * wr + vi * wi;
-                si[j] += vr * wi - vi * wr;
-            }
+            const double* v = V + (int64_t)(j0 + j) * vstride;
+            vr[j] = v[i];
+            vi[j] = v[i + plane];
+        }
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            sr[j] += vr[j] * wr + vi[j] * wi;
+            si[j] += vr[j] * wi - vi[j] * wr;
         }
     }
-    block_sums_out<KC>(sr, si, kc, j0, part, sh);
+    block_sums_out<KC>(sr, si, KC, j0, part, sh);
+}
+// launch multidot_w1_partial<kc> (1 <= kc <= KC)
+template <int KC>
+static void launch_multidot_w1(int kc, int nb, hipStream_t st, const double* V, int64_t vstride,
+                               int j0, const double* w, int64_t n, int64_t plane, double* part,
+                               const int* stop) {
+    if constexpr (KC > 1) {
+        if (kc < KC) {
+            launch_multidot_w1<KC - 1>(kc, nb, st, V, vstride, j0, w, n, plane, part, stop);
+            return;
+        }
+    }
+    multidot_w1_partial<KC><<<nb, RB, 0, st>>>(V, vstride, j0, w, n, plane, part, stop);
 }
 
-// One pass of w -= sum_j V_j h[j] (j < k <= KC) that also forms the block
-// partials of the next projections <V_j, w> of the updated w (the second
-// Gram-Schmidt pass needs exactly these), part[(j * nb + b) * 2], and in group
-// k the partials of |w|^2 after and before the update.
+// One pass of w -= sum_j V_j h[j] (j < KC, the exact vector count) that
+// also forms the block partials of the next projections <V_j, w> of the
+// updated w (the second Gram-Schmidt pass needs exactly these),
+// part[(j * nb + b) * 2], and in group KC the partials of |w|^2 after and
+// before the update.
 template <int KC>
 __global__ __launch_bounds__(RB) void multiaxpy_dot_partial(const double* __restrict__ V,
-                                                           int64_t vstride, int k,
+                                                           int64_t vstride,
                                                            const double* __restrict__ h,
                                                            double* __restrict__ w, int64_t n,
                                                            int64_t plane,
                                                            double* __restrict__ part,
                                                            const int* stop) {
+    constexpr int k = KC;
     if (stop && *stop) return;
     __shared__ double sh[16];
     double hr[KC], hi[KC], sr[KC], si[KC];
 #pragma unroll
     for (int j = 0; j < KC; ++j) {
-        hr[j] = j < k ? h[2 * j] : 0.0;
-        hi[j] = j < k ? h[2 * j + 1] : 0.0;
+        hr[j] = h[2 * j];
+        hi[j] = h[2 * j + 1];
         sr[j] = si[j] = 0.0;
     }
     double s_before = 0.0, s_after = 0.0;
@@ -229,22 +249,18 @@ __global__ __launch_bounds__(RB) void multiaxpy_dot_partial(const double* __rest
         s_before += ar * ar + ai * ai;
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
-            if (j < k) {
-                vr[j] = V[(int64_t)j * vstride + i];
-                vi[j] = V[(int64_t)j * vstride + i + plane];
-                ar -= vr[j] * hr[j] - vi[j] * hi[j];
-                ai -= vr[j] * hi[j] + vi[j] * hr[j];
-            }
+            vr[j] = V[(int64_t)j * vstride + i];
+            vi[j] = V[(int64_t)j * vstride + i + plane];
+            ar -= vr[j] * hr[j] - vi[j] * hi[j];
+            ai -= vr[j] * hi[j] + vi[j] * hr[j];
         }
         w[i] = ar;
         w[i + plane] = ai;
         s_after += ar * ar + ai * ai;
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
-            if (j < k) {
-                sr[j] += vr[j] * ar + vi[j] * ai;
-                si[j] += vr[j] * ai - vi[j] * ar;
-            }
+            sr[j] += vr[j] * ar + vi[j] * ai;
+            si[j] += vr[j] * ai - vi[j] * ar;
         }
     }
     block_sums_out<KC>(sr, si, k, 0, part, sh);
@@ -254,6 +270,20 @@ __global__ __launch_bounds__(RB) void multiaxpy_dot_partial(const double* __rest
         part[o] = a;
         part[o + 1] = b;
     }
+}
+
+// launch multiaxpy_dot_partial<k> (1 <= k <= KC)
+template <int KC>
+static void launch_multiaxpy_dot(int k, int nb, hipStream_t st, const double* V, int64_t vstride,
+                                 const double* h, double* w, int64_t n, int64_t plane,
+                                 double* part, const int* stop) {
+    if constexpr (KC > 1) {
+        if (k < KC) {
+            launch_multiaxpy_dot<KC - 1>(k, nb, st, V, vstride, h, w, n, plane, part, stop);
+            return;
+        }
+    }
+    multiaxpy_dot_partial<KC><<<nb, RB, 0, st>>>(V, vstride, h, w, n, plane, part, stop);
 }
 
 // h[j] = <V_j, w>: grid (nb, k)
@@ -288,8 +318,8 @@ void k_multidot(Ctx* ctx, const double* V, int64_t vstride, int k, const double*
     if (n >= (int64_t)RB * 64) {
         // long vectors: w read once per chunk of eight Krylov vectors
         for (int j0 = 0; j0 < k; j0 += 8)
-            multidot_w1_partial<8><<<nb, RB, 0, ctx->stream>>>(V, vstride, j0, std::min(8, k - j0),
-                                                               w, n, plane, part, ctx->kstop);
+            launch_multidot_w1<8>(std::min(8, k - j0), nb, ctx->stream, V, vstride, j0, w, n,
+                                  plane, part, ctx->kstop);
     } else {
         nb = std::min(nb, 128);
         multidot_partial<<<dim3(nb, k), RB, 0, ctx->stream>>>(V, vstride, w, n, plane, part,
@@ -305,31 +335,31 @@ bool k_multiaxpy_dot(Ctx* ctx, const double* V, int64_t vstride, int k, double* 
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
     const int nb = red_blocks(n);
-    if (k <= 8)
-        multiaxpy_dot_partial<8><<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
-                                                             ctx->kstop);
-    else
-        multiaxpy_dot_partial<16><<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
-                                                              ctx->kstop);
+    launch_multiaxpy_dot<16>(k, nb, ctx->stream, V, vstride, h, w, n, plane, part, ctx->kstop);
     sum_partials<<<k + 1, RB, 0, ctx->stream>>>(part, nb, 2, h, ctx->kstop);
     FTD_HIP(hipGetLastError());
     return true;
 }
 
 // w -= sum_j V_j h[j], then block partials of |w|^2 (one pass over w); not
-// at all when the first pass kept enough of w (skip[0] > thr2 * skip[1])
+// at all when the first pass kept enough of w (skip[0] > thr2 * skip[1]).
+// KC > 0: exactly KC vectors (the loop unrolls and every load is issued
+// up front); KC = 0: k vectors.
+template <int KC>
 __global__ void multiaxpy_nrm_partial(const double* __restrict__ V, int64_t vstride, int k,
                                       const double* __restrict__ h, double* __restrict__ w,
                                       int64_t n, int64_t plane, double* __restrict__ part,
                                       const int* stop, const double* skip, double thr2) {
     if (stop && *stop) return;
     if (skip && skip[0] > thr2 * skip[1]) return;
+    const int kk = KC > 0 ? KC : k;
     __shared__ double sh[16];
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double ar = w[i], ai = w[i + plane];
-        for (int j = 0; j < k; ++j) {
+#pragma unroll
+        for (int j = 0; j < kk; ++j) {
             const double hr = h[2 * j], hi = h[2 * j + 1];
             const double vr = V[(int64_t)j * vstride + i], vi = V[(int64_t)j * vstride + i + plane];
             ar -= vr * hr - vi * hi;
@@ -342,13 +372,34 @@ __global__ void multiaxpy_nrm_partial(const double* __restrict__ V, int64_t vstr
     s = block_sum(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
+// launch multiaxpy_nrm_partial<k> for 1 <= k <= KC, the generic <0> above
+template <int KC>
+static void launch_multiaxpy_nrm(int k, int nb, hipStream_t st, const double* V, int64_t vstride,
+                                 const double* h, double* w, int64_t n, int64_t plane,
+                                 double* part, const int* stop, const double* skip,
+                                 double thr2) {
+    if (k > KC || k < 1) {
+        multiaxpy_nrm_partial<0><<<nb, RB, 0, st>>>(V, vstride, k, h, w, n, plane, part, stop,
+                                                    skip, thr2);
+        return;
+    }
+    if constexpr (KC > 1) {
+        if (k < KC) {
+            launch_multiaxpy_nrm<KC - 1>(k, nb, st, V, vstride, h, w, n, plane, part, stop, skip,
+                                         thr2);
+            return;
+        }
+    }
+    multiaxpy_nrm_partial<KC><<<nb, RB, 0, st>>>(V, vstride, k, h, w, n, plane, part, stop, skip,
+                                                 thr2);
+}
 int k_multiaxpy_nrm2_part(Ctx* ctx, const double* V, int64_t vstride, int k, const double* h,
                           double* w, int64_t n, int64_t plane, const double* skip, double thr2) {
     const int nb = red_blocks(n);
     ctx->ws_red.ensure(ctx, sizeof(double) * 2 * RMAXB * (kMaxKrylov + 1));
     double* part = ctx->ws_red.as<double>();
-    multiaxpy_nrm_partial<<<nb, RB, 0, ctx->stream>>>(V, vstride, k, h, w, n, plane, part,
-                                                      ctx->kstop, skip, thr2);
+    launch_multiaxpy_nrm<16>(k, nb, ctx->stream, V, vstride, h, w, n, plane, part, ctx->kstop,
+                             skip, thr2);
     FTD_HIP(hipGetLastError());
     return nb;
 }
