@@ -201,7 +201,6 @@ void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double 
                     double thr2 = 0.0);
 void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane,
                     float* out32 = nullptr);
-void k_set_alpha(Ctx* ctx, KrylovDev kd, int k);
 void k_krylov_reset(Ctx* ctx, KrylovDev kd);
 
 // ----------------------------------------------------------------- QR / SVD

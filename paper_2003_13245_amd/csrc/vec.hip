@@ -798,10 +798,6 @@ __global__ void lanczos_post_kernel(KrylovDev kd, int n, double* w, int64_t len,
         }
     }
 }
-__global__ void set_alpha_kernel(KrylovDev kd, int k) {
-    if (kd.flag[3]) return;
-    kd.alpha[k] = kd.h[2 * k];
-}
 __global__ void krylov_reset_kernel(KrylovDev kd) {
     kd.flag[0] = 0;
     kd.flag[1] = 0;
@@ -823,10 +819,6 @@ void k_tridiag_expm(Ctx* ctx, KrylovDev kd, int k, double zr, double zi, double 
 void k_lanczos_post(Ctx* ctx, KrylovDev kd, int k, double* w, int64_t n, int64_t plane,
                     float* out32) {
     lanczos_post_kernel<<<grid_for(n), 256, 0, ctx->stream>>>(kd, k, w, n, plane, out32);
-    FTD_HIP(hipGetLastError());
-}
-void k_set_alpha(Ctx* ctx, KrylovDev kd, int k) {
-    set_alpha_kernel<<<1, 1, 0, ctx->stream>>>(kd, k);
     FTD_HIP(hipGetLastError());
 }
 
