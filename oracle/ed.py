@@ -150,3 +150,91 @@ def thermal_state_vector(ed, beta):
     """exp(-beta H / 2) applied to the purified identity, as the dense matrix
     M = exp(-beta H/2) (P index rows, Q index columns).  Tests only."""
     return (ed.U * np.exp(-0.5 * beta * ed.E)) @ ed.U.T
+
+
+# ------------------------------------------------------ exact mobility gradient
+# Derivative of the Kubo mobility of the truncated model with respect to the
+# shared mode parameters, exactly (no finite differences, no TDVP): mu is
+# (beta / e0) times the trapezoid sum of Re C(t_k) on the run grid (the
+# mobility passage, Eq. (kubo)), C(t) = Tr[e^{-beta H} e^{iHt} j e^{-iHt} j] /
+# Z.  H and K (j = (e0 R / i) K) are affine in each omega and each g at fixed
+# other parameters, so dH/dx and dK/dx are exact differences of two builds.
+# The derivative of a function f(H) along A is, in the eigenbasis of H,
+# Gamma_f o (U^T A U) with Gamma_f[a, b] the divided difference
+# (f(E_a) - f(E_b)) / (E_a - E_b) (f'(E_a) where E_a = E_b): the
+# Daleckii-Krein formula, here for f = exp(s E), s = -beta and -+ i t.
+
+
+def _divided_exp(E, s):
+    """Gamma[a, b] = (exp(s E_a) - exp(s E_b)) / (E_a - E_b), s exp(s E_a)
+    where E_a == E_b; expm1 keeps nearly equal energies accurate."""
+    d = E[:, None] - E[None, :]
+    eb = np.exp(s * E)[None, :]
+    safe = np.where(d == 0.0, 1.0, d)
+    G = eb * np.expm1(s * d) / safe
+    return np.where(d == 0.0, s * np.exp(s * E)[:, None] * np.ones_like(d), G)
+
+
+def _parameter_directions(model):
+    """[(name, index, dH, dK)] for every shared mode parameter: the exact
+    change of the dense H and K per unit change of that parameter."""
+    import dataclasses
+    H0, K0, _ = build(model)
+    out = []
+    for name in ("omega_loc", "g_loc", "omega_nl", "g_nl"):
+        vals = list(getattr(model, name))
+        for i in range(len(vals)):
+            up = dataclasses.replace(model, **{name: vals[:i] + [vals[i] + 1.0] + vals[i + 1:]})
+            H1, K1, _ = build(up)
+            out.append((name, i, H1 - H0, K1 - K0))
+    return out
+
+
+def mobility_gradient(model, beta, dt, n_steps):
+    """Exact mu (a.u.) on the grid t_k = k dt, k = 0..n_steps (trapezoid), and
+    {"omega_loc", "g_loc", "omega_nl", "g_nl"} -> arrays of d mu / d x."""
+    H, K, _ = build(model)
+    E, U = np.linalg.eigh(H)
+    E = E - E[0]                       # a shift of H changes no C(t)
+    c = model.e0 * model.R / 1j        # j = c K
+    Kt = U.T @ K @ U
+    p = np.exp(-beta * E)
+    Z = p.sum()
+    times = np.arange(n_steps + 1) * dt
+    wq = np.full(n_steps + 1, dt)
+    wq[0] = wq[-1] = 0.5 * dt
+    Gb = _divided_exp(E, -beta)
+    # per time: V = exp(-iHt), its divided differences, C(t)
+    per_t = []
+    C = np.zeros(n_steps + 1, dtype=complex)
+    for k, t in enumerate(times):
+        v = np.exp(-1j * E * t)
+        jt = c * Kt
+        # G(t) = Tr[P V^H j V j] in the eigenbasis (P, V diagonal)
+        M = (np.conj(v)[:, None] * jt) * v[None, :]           # V^H j V
+        G = np.sum(p[:, None] * M * jt.T)                      # Tr[P M j]
+        C[k] = G / Z
+        per_t.append((v, jt, M, _divided_exp(E, -1j * t), _divided_exp(E, 1j * t)))
+    mu = beta / model.e0 * float(np.sum(wq * C.real))
+    grads = {"omega_loc": [], "g_loc": [], "omega_nl": [], "g_nl": []}
+    for name, i, dH, dK in _parameter_directions(model):
+        At = U.T @ dH @ U
+        dj = c * (U.T @ dK @ U)
+        dP = Gb * At                                           # d exp(-beta H)
+        dZ = float(np.trace(dP).real)
+        dmu = 0.0
+        for k, (v, jt, M, Gm, Gp) in enumerate(per_t):
+            dV = Gm * At                                       # d exp(-iHt)
+            dVh = Gp * At                                      # d exp(+iHt)
+            Pm = p[:, None]
+            Vh = np.conj(v)
+            # the five terms of d Tr[P V^H j V j]
+            dG = np.trace(dP @ (M @ jt))
+            dG += np.trace(Pm * ((dVh @ jt) * v[None, :]) @ jt)
+            dG += np.trace(Pm * (Vh[:, None] * (jt @ dV)) @ jt)
+            dG += np.trace(Pm * ((Vh[:, None] * dj) * v[None, :]) @ jt)
+            dG += np.trace(Pm * M @ dj)
+            dC = (dG - C[k] * dZ) / Z
+            dmu += wq[k] * dC.real
+        grads[name].append(beta / model.e0 * dmu)
+    return mu, {k: np.array(v) for k, v in grads.items()}
