@@ -2,7 +2,9 @@
 HIP library: the mean free path (mean-free-path passage: v = sqrt(<j j>),
 tau = (1/2) int |Re C / Re C(0)| dt) and the hopping-limit correlation of
 Eq. (ct) (the Fermi-golden-rule comparator), both host entry points of the
-C ABI, fed with C(t) from the GPU's own preparation and propagation."""
+C ABI, fed with C(t) from the GPU's own preparation and propagation; and
+the uncoupled ring, whose C(t) the GPU pipeline must reproduce as the
+tight-binding closed form at every time."""
 import sys
 
 import numpy as np
@@ -79,3 +81,31 @@ def test_hopping_limit_of_gpu_correlation(ctx):
         say(f"[cmp] V={V:g}: GPU C(t) vs hopping limit {err:.2e} (conjugate form {err_conj:.2e})")
         assert err < 3e-2
         assert err_conj > 0.3
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.5])
+def test_uncoupled_ring_closed_form_on_gpu(ctx, beta):
+    """With g = 0 the phonons decouple and j commutes with the electronic
+    Hamiltonian of the ring, so C(t) is constant:
+    (2 e0 V R)^2 sum_k sin^2 k e^{-2 beta V cos k} / sum_k e^{-2 beta V cos k},
+    k = 2 pi n / N, and mu = beta C t_max / e0.  The whole GPU pipeline
+    (growth, one-site steps, j|Psi>, real-time steps, overlaps, Kubo sum)
+    against that closed form.  The oracle's own pipeline at these settings
+    is off by 3.5e-6 and 2.3e-6 on C(t), 1.3e-6 and 4.5e-7 on mu (the
+    Taylor-4 growth steps, which the GPU takes the same way), the GPU's by
+    5.5e-7 (beta 1) and 3.7e-6 (beta 0.5) on C(t); a wrong beta, V, R or e0
+    is off by O(1)."""
+    from paper_2003_13245_amd import api
+    m = W.Model(n_mol=4, periodic=1, omega_loc=[1.0], g_loc=[0.0], omega_nl=[], g_nl=[],
+                levels_loc=2, levels_nl=1, V=1.0, R=1.3, e0=1.0)
+    dt, n_steps = 0.1, 10
+    say(f"[closed form] beta={beta}")
+    _, C = _gpu_corr(ctx, m, beta, 20, 20, 64, dt, n_steps)
+    k = 2 * np.pi * np.arange(m.n_mol) / m.n_mol
+    w = np.exp(-2 * beta * m.V * np.cos(k))
+    exact = (2 * m.e0 * m.V * m.R) ** 2 * (np.sin(k) ** 2 * w).sum() / w.sum()
+    err = float(np.abs(C - exact).max() / exact)
+    say(f"[closed form] beta={beta} err {err:.3e}")
+    assert err <= 1e-5, err
+    mu = api.mobility(C, dt, beta, m.e0)[0]
+    assert abs(mu - beta / m.e0 * exact * n_steps * dt) <= 1e-5 * beta * exact * n_steps * dt
