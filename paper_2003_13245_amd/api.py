@@ -556,10 +556,26 @@ def svd_trunc(ctx, T, D, cutoff=1e-10, s_left=True):
     return L, R
 
 
+def _check_site_vector(H, psi, site, x):
+    """The C ABI reads psi's site shape from x without a length: refuse an x
+    of another size here (an out-of-range site is left to the library)."""
+    dims, _ = H.info()
+    L = len(dims)
+    if not 0 <= int(site) < L:
+        return
+    bonds = psi.info()["bond_dims"]
+    dl = 1 if site == 0 else bonds[site - 1]
+    dr = 1 if site == L - 1 else bonds[site]
+    want = dl * int(dims[site]) ** 2 * dr
+    if x.size != want:
+        raise ValueError(f"site {site} holds {want} elements, x has {x.size}")
+
+
 def heff_expm(ctx, H, psi, site, x, z, tol=1e-14, mmax=40, n_repeat=1):
     """exp(z H_eff) x at `site` by the library's Krylov exponential; returns
     (y, Krylov vector count)."""
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    _check_site_vector(H, psi, site, x)
     xb = np.empty(2 * x.size)
     xb[0::2] = x.real.reshape(-1)
     xb[1::2] = x.imag.reshape(-1)
@@ -574,6 +590,7 @@ def heff_expm(ctx, H, psi, site, x, z, tol=1e-14, mmax=40, n_repeat=1):
 
 def heff_apply(ctx, H, psi, site, x, n_repeat=1):
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    _check_site_vector(H, psi, site, x)
     xb = np.empty(2 * x.size)
     xb[0::2] = x.real.reshape(-1)
     xb[1::2] = x.imag.reshape(-1)

@@ -141,3 +141,26 @@ def test_coherent_length_host_entry(abi):
     import ctypes
     L = ctypes.c_double()
     assert abi.lib.ftd_coherent_length(abi._dptr(np.zeros(2)), 0, ctypes.byref(L)) != 0
+
+
+def test_site_vector_size_is_checked_before_the_call():
+    """heff_apply / heff_expm hand x to the C ABI without a length: the binding
+    refuses an x whose size is not the site's Dl d^2 Dr (an out-of-range site
+    is left to the library's own error)."""
+    import numpy as np
+    from paper_2003_13245_amd import api
+
+    class MpoStub:
+        def info(self):
+            return np.array([2, 3, 3, 2]), None
+
+    class MpsStub:
+        def info(self):
+            return {"bond_dims": [4, 5, 6]}
+
+    H, psi = MpoStub(), MpsStub()
+    for site, n in ((0, 1 * 4 * 4), (1, 4 * 9 * 5), (2, 5 * 9 * 6), (3, 6 * 4 * 1)):
+        api._check_site_vector(H, psi, site, np.zeros(n))
+        with pytest.raises(ValueError):
+            api._check_site_vector(H, psi, site, np.zeros(n + 1))
+    api._check_site_vector(H, psi, 4, np.zeros(3))
